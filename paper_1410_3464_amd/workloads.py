@@ -1,0 +1,312 @@
+"""Seeded synthetic problem descriptions for the coupled reactive-transport step.
+
+This module only builds inputs: lattice geometry, node types, initial densities
+and concentrations, and the parameter sets.  It contains none of the step's
+arithmetic, so the GPU library and the CPU oracle can both consume what it
+produces without sharing any of the method.
+
+Problem layout (all arrays row-major, index ``y*nx + x``):
+
+* ``type0`` uint8 ``[ny, nx]``: 0 fluid, 1 inert solid, 2 dissolvable solid D,
+  3 precipitate solid F (the node types of Fig. 2 of the paper).
+* ``V0`` float64 ``[ny, nx]``: solid volume at D/F nodes, precipitate fraction at fluid nodes.
+* ``rho1``, ``rho2`` float64 ``[ny, nx]``: initial liquid- and gas-component densities.
+* ``C0`` float64 ``[n_species, ny, nx]``: initial concentrations (used at liquid nodes only).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+FLUID, SOLID_INERT, SOLID_D, SOLID_F = 0, 1, 2, 3
+
+# Carnahan-Starling parameter sets named in the text after Eq. 13: the original
+# (a=1, b=4, R=1) and the one the paper adopts because the two-component system
+# diverges at the small vapour density of the first (a=0.09926, b=0.18727, R=0.2).
+EOS_ORIGINAL = (1.0, 4.0, 1.0)
+EOS_PAPER = (0.09926, 0.18727, 0.2)
+
+# Coexistence densities at T = 0.75 T_c from Maxwell's equal-area rule, stored as
+# constants so that this module stays free of the EOS; a CPU test recomputes them.
+RHO_L_075 = 0.3331630195715653     # EOS_ORIGINAL
+RHO_V_075 = 0.01454506511014443
+RHO_L_075_PAPER = 7.116206964736306  # EOS_PAPER
+RHO_V_075_PAPER = 0.3106758180173559
+
+
+@dataclass
+class Species:
+    name: str
+    tau_g: float = 1.0
+    J0: float = 0.9
+
+
+@dataclass
+class HomRxn:
+    """Homogeneous reaction (Eq. 5a, 5c, or first order).
+
+    kind: "first_order" (R = k C_re0), "r1_gas" (R = k (C_re0 - C_pr0 sqrt(rho2/M_gas)/K_eq),
+    with half a mole of gas per mole moved from the liquid to the gas component),
+    "bimolecular" (R = k C_re0 C_re1).  Indices refer to the species list; -1 = none.
+    """
+
+    kind: str
+    re: tuple = (-1, -1)
+    pr: tuple = (-1, -1)
+    k: float = 0.0
+    K_eq: float = 1.0
+    M_gas: float = 1.0
+
+
+@dataclass
+class HetRxn:
+    """Heterogeneous surface reaction (Eq. 29-31, A2).
+
+    mode: "consumes" (solid node volume decreases, R2-like), "grows" (precipitate
+    accumulates at the liquid node, R4-like), "mineral" (solid node volume follows
+    the sign of the flux, Appendix A.3).  surface: solid types it acts on.
+    """
+
+    reactant: int
+    product: int = -1
+    surface: tuple = (SOLID_D,)
+    mode: str = "consumes"
+    irreversible: bool = True
+    k: float = 0.0
+    C_eq: float = 0.0
+    molar_volume: float = 1.0
+
+
+@dataclass
+class Problem:
+    name: str
+    nx: int
+    ny: int
+    periodic_x: bool
+    periodic_y: bool
+    tau: tuple = (1.0, 1.0)
+    w_adh: tuple = (0.0, 0.0)
+    gbody: tuple = (0.0, 0.0)
+    a: float = 1.0
+    b: float = 4.0
+    R: float = 1.0
+    T: float = 0.0
+    G11: float = -1.0
+    G12: float = 0.0
+    G21: float = 0.0
+    a0: float = 0.005
+    rho10: float = 0.0
+    rho20: float = 0.003
+    liquid_frac: float = 0.5
+    species: list = field(default_factory=list)
+    hom: list = field(default_factory=list)
+    het: list = field(default_factory=list)
+    type0: np.ndarray = None
+    V0: np.ndarray = None
+    rho1: np.ndarray = None
+    rho2: np.ndarray = None
+    C0: np.ndarray = None
+    steps: int = 0
+
+    @property
+    def n_species(self):
+        return len(self.species)
+
+    def copy(self, **kw):
+        return dataclasses.replace(self, **kw)
+
+
+def critical_temperature(a, b, R):
+    """T_c from the definitions of a and b in the text after Eq. 12."""
+    return (0.1873 / 0.4963) * a / (b * R)
+
+
+def paper_rho10(a0=0.005):
+    """rho_10 = -0.008 / ln(a0) (text after Eq. 15, natural logarithm)."""
+    return -0.008 / math.log(a0)
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def _disk_mask(nx, ny, cx, cy, r, periodic_x=True, periodic_y=True):
+    x = np.arange(nx)[None, :].astype(np.float64)
+    y = np.arange(ny)[:, None].astype(np.float64)
+    dx = x - cx
+    dy = y - cy
+    if periodic_x:
+        dx = (dx + nx / 2) % nx - nx / 2
+    if periodic_y:
+        dy = (dy + ny / 2) % ny - ny / 2
+    return dx * dx + dy * dy <= r * r
+
+
+def _stamp_disk(mask, cx, cy, r, periodic_x, periodic_y):
+    """Boolean disk of radius r centred at (cx, cy), stamped by bounding box."""
+    ny, nx = mask.shape
+    out = np.zeros_like(mask)
+    ri = int(math.ceil(r))
+    xs = np.arange(int(math.floor(cx)) - ri, int(math.floor(cx)) + ri + 2)
+    ys = np.arange(int(math.floor(cy)) - ri, int(math.floor(cy)) + ri + 2)
+    dx = xs[None, :] - cx
+    dy = ys[:, None] - cy
+    inside = dx * dx + dy * dy <= r * r
+    if periodic_x:
+        xs = xs % nx
+    if periodic_y:
+        ys = ys % ny
+    okx = (xs >= 0) & (xs < nx)
+    oky = (ys >= 0) & (ys < ny)
+    inside = inside & okx[None, :] & oky[:, None]
+    yy, xx = np.nonzero(inside)
+    out[ys[yy], xs[xx]] = True
+    return out, ys[yy], xs[xx]
+
+
+def config0(seed=0):
+    """96x64 periodic box: a droplet of radius 16 in its vapour at T = 0.75 T_c, a
+    non-condensable gas at 0.1, one dissolvable disk of radius 10 at (20, 32); species
+    A, B with A -> B (k = 1e-3) in the liquid and surface dissolution consuming B
+    (k_s = 1e-2).  The fluid uses the paper's adopted EOS set."""
+    nx, ny = 96, 64
+    a, b, R = EOS_PAPER
+    T = 0.75 * critical_temperature(a, b, R)
+    type0 = np.zeros((ny, nx), np.uint8)
+    solid = _disk_mask(nx, ny, 20.0, 32.0, 10.0)
+    type0[solid] = SOLID_D
+    V0 = np.where(solid, 1.0, 0.0)
+    drop = _disk_mask(nx, ny, 48.0, 32.0, 16.0)
+    rho1 = np.where(drop, RHO_L_075_PAPER, RHO_V_075_PAPER)
+    rho2 = np.full((ny, nx), 0.1)
+    rng = _rng(seed)
+    n1 = rng.uniform(-1e-4, 1e-4, size=(ny, nx))
+    n2 = rng.uniform(-1e-4, 1e-4, size=(ny, nx))
+    fl = type0 == FLUID
+    rho1 = np.where(fl, rho1 + n1, 0.0)
+    rho2 = np.where(fl, rho2 + n2, 0.0)
+    C0 = np.zeros((2, ny, nx))
+    C0[0] = 1.0
+    return Problem(
+        name="droplet-96x64", nx=nx, ny=ny, periodic_x=True, periodic_y=True,
+        tau=(1.0, 1.0), a=a, b=b, R=R, T=T, G11=-1.0, G12=0.5, G21=0.5,
+        a0=0.005, rho10=paper_rho10(0.005), rho20=0.003,
+        species=[Species("A", 1.0, 0.9), Species("B", 1.0, 0.9)],
+        hom=[HomRxn("first_order", re=(0, -1), pr=(1, -1), k=1e-3)],
+        het=[HetRxn(reactant=1, product=-1, surface=(SOLID_D,), mode="consumes",
+                    irreversible=True, k=1e-2, C_eq=0.0, molar_volume=1.0)],
+        type0=type0, V0=V0, rho1=rho1, rho2=rho2, C0=C0, steps=2000,
+    )
+
+
+def porous_medium(nx, ny, seed, porosity=0.55, rmin=8.0, rmax=24.0, reactive_frac=0.2,
+                  gas_frac=0.3, bmin=6.0, bmax=16.0):
+    """Random overlapping disks (periodic in x) until the porosity target; grains
+    chosen in random order become dissolvable (D) until the reactive fraction of solid
+    nodes is reached, the rest inert; vapour bubbles on pore nodes until gas_frac of
+    the pore space.  Returns (type0, gas) as arrays."""
+    rng = _rng(seed)
+    grain_id = np.full((ny, nx), -1, np.int64)
+    n_solid = 0
+    target = (1.0 - porosity) * nx * ny
+    gid = 0
+    while n_solid < target:
+        cx = rng.uniform(0, nx)
+        cy = rng.uniform(0, ny)
+        r = rng.uniform(rmin, rmax)
+        _, ys, xs = _stamp_disk(grain_id, cx, cy, r, True, False)
+        new = grain_id[ys, xs] < 0
+        grain_id[ys[new], xs[new]] = gid
+        n_solid += int(new.sum())
+        gid += 1
+    type0 = np.where(grain_id >= 0, SOLID_INERT, FLUID).astype(np.uint8)
+    counts = np.bincount(grain_id[grain_id >= 0].ravel(), minlength=gid)
+    order = rng.permutation(gid)
+    need = reactive_frac * n_solid
+    got = 0
+    reactive = np.zeros(gid, bool)
+    for g_ in order:
+        if got >= need:
+            break
+        if counts[g_] == 0:
+            continue
+        reactive[g_] = True
+        got += counts[g_]
+    sel = (grain_id >= 0) & reactive[np.maximum(grain_id, 0)]
+    type0[sel] = SOLID_D
+    pore = type0 == FLUID
+    n_pore = int(pore.sum())
+    gas = np.zeros((ny, nx), bool)
+    n_gas = 0
+    pys, pxs = np.nonzero(pore)
+    while n_gas < gas_frac * n_pore:
+        i = int(rng.integers(0, n_pore))
+        cx, cy = float(pxs[i]), float(pys[i])
+        r = rng.uniform(bmin, bmax)
+        _, ys, xs = _stamp_disk(gas, cx, cy, r, True, False)
+        ok = pore[ys, xs] & ~gas[ys, xs]
+        gas[ys[ok], xs[ok]] = True
+        n_gas += int(ok.sum())
+    return type0, gas, rng
+
+
+def config1(nx=1024, ny=512, seed=1, steps=20000):
+    """Porous medium: porosity 0.55, 20% of solid dissolvable, 30% of the pore space
+    vapour bubbles, body force 1e-6 along x, periodic in x with walls in y; species
+    A, B, E, F with A <-> B + C(g) (k1 = 0.1, K_eq = 1, M_C = 1e-3), B + E -> F
+    (k3 = 1e-5), surface dissolution of D by B -> E (1e-3) and precipitation of F on
+    D or F (1e-4, C_sa = 0)."""
+    a, b, R = EOS_PAPER
+    T = 0.75 * critical_temperature(a, b, R)
+    type0, gas, rng = porous_medium(nx, ny, seed)
+    fl = type0 == FLUID
+    rho1 = np.where(gas, RHO_V_075_PAPER, RHO_L_075_PAPER)
+    rho2 = np.full((ny, nx), 0.1)
+    n1 = rng.uniform(-1e-4, 1e-4, size=(ny, nx))
+    n2 = rng.uniform(-1e-4, 1e-4, size=(ny, nx))
+    rho1 = np.where(fl, rho1 + n1, 0.0)
+    rho2 = np.where(fl, rho2 + n2, 0.0)
+    V0 = np.where(type0 == SOLID_D, 1.0, 0.0)
+    C0 = np.zeros((4, ny, nx))
+    C0[0] = 1.0
+    return Problem(
+        name=f"porous-{nx}x{ny}", nx=nx, ny=ny, periodic_x=True, periodic_y=False,
+        tau=(1.0, 1.0), gbody=(1e-6, 0.0), a=a, b=b, R=R, T=T, G11=-1.0, G12=0.5, G21=0.5,
+        a0=0.005, rho10=paper_rho10(0.005), rho20=0.003,
+        species=[Species("A"), Species("B"), Species("E"), Species("F")],
+        hom=[HomRxn("r1_gas", re=(0, -1), pr=(1, -1), k=1e-1, K_eq=1.0, M_gas=1e-3),
+             HomRxn("bimolecular", re=(1, 2), pr=(3, -1), k=1e-5)],
+        het=[HetRxn(reactant=1, product=2, surface=(SOLID_D,), mode="consumes",
+                    irreversible=True, k=1e-3, C_eq=0.0, molar_volume=1.0),
+             HetRxn(reactant=3, product=-1, surface=(SOLID_D, SOLID_F), mode="grows",
+                    irreversible=True, k=1e-4, C_eq=0.0, molar_volume=1.0)],
+        type0=type0, V0=V0, rho1=rho1, rho2=rho2, C0=C0, steps=steps,
+    )
+
+
+def config2(n=4096, seed=2, steps=10000):
+    """The porous-medium generator at 4096 x 4096 (the throughput workload)."""
+    p = config1(nx=n, ny=n, seed=seed, steps=steps)
+    p.name = f"porous-{n}x{n}"
+    return p
+
+
+def uniform_problem(nx, ny, periodic_x=True, periodic_y=True, rho1=1.0, rho2=0.0,
+                    species=(), C0=None, ideal=True, **kw):
+    """A uniform fluid box.  With ideal=True the liquid component is an ideal gas
+    with R T = 1/3 and a = b = 0, so its effective mass vanishes (no cohesion)."""
+    type0 = np.zeros((ny, nx), np.uint8)
+    r1 = np.full((ny, nx), float(rho1))
+    r2 = np.full((ny, nx), float(rho2))
+    ns = len(species)
+    C = np.zeros((ns, ny, nx)) if C0 is None else np.asarray(C0, np.float64).reshape(ns, ny, nx)
+    base = dict(name=f"uniform-{nx}x{ny}", nx=nx, ny=ny, periodic_x=periodic_x,
+                periodic_y=periodic_y, species=list(species), type0=type0,
+                V0=np.zeros((ny, nx)), rho1=r1, rho2=r2, C0=C)
+    if ideal:
+        base.update(a=0.0, b=0.0, R=1.0, T=1.0 / 3.0, G11=-1.0, G12=0.0, G21=0.0)
+    base.update(kw)
+    return Problem(**base)
