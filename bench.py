@@ -1,0 +1,184 @@
+"""Throughput of the coupled reactive-transport LB step on one MI355X.
+
+Workload: the porous-medium generator at 4096 x 4096 (porosity 0.55, 20% of the
+solid dissolvable, 30% of the pore space vapour, two flow components, four
+species, two homogeneous and two surface reactions), FP32 by default.  One step
+is one launch of the fused step kernel over the whole lattice; the populations
+are resident in HBM before the timed region starts.
+
+Prints one JSON line: MLUPS (nx*ny*steps/s/1e6), the HBM roofline of the step
+kernel (algorithmic bytes per launch / kernel time from HIP events on the
+library's stream), and the FP64 CPU oracle timed on a bounded sample of the
+same lattice on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "coupled-step MLUPS & %HBM roofline on 1 MI355X; serving p50/p99 vs plain"
+
+
+def algorithmic_bytes(F, prob, esz):
+    """Bytes one step must move at minimum: every flow population of a fluid node
+    read and written once, every solute population of a liquid node read and
+    written once, the node-type byte read and written, and the FP64 solid /
+    precipitate volume read and written at liquid-solid interface nodes."""
+    t = F["type"]
+    fluid = t == 0
+    liq = F["liquid"].astype(bool)
+    ns = prob.n_species
+    reactive = (t == 2) | (t == 3)
+    # D2Q5 neighbours (periodicity as in the problem)
+    def shifted(m, dx, dy):
+        out = np.roll(m, (dy, dx), axis=(0, 1))
+        if not prob.periodic_x:
+            if dx > 0: out[:, :dx] = False
+            if dx < 0: out[:, dx:] = False
+        if not prob.periodic_y:
+            if dy > 0: out[:dy, :] = False
+            if dy < 0: out[dy:, :] = False
+        return out
+    near_liq = np.zeros_like(liq)
+    near_rs = np.zeros_like(liq)
+    for dx, dy in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+        near_liq |= shifted(liq, dx, dy)
+        near_rs |= shifted(reactive, dx, dy)
+    interface = (reactive & near_liq) | (liq & near_rs)
+    n = t.size
+    b = (int(fluid.sum()) * 36 * esz + int(liq.sum()) * 10 * ns * esz + 2 * n + 16 * int(interface.sum()))
+    counts = dict(fluid=int(fluid.sum()), liquid=int(liq.sum()), interface=int(interface.sum()), nodes=n)
+    return b, counts
+
+
+def cpu_baseline(prob, steps):
+    """The FP64 oracle, as it stands, single-threaded on the host: `steps` steps of
+    the same lattice."""
+    from oracle import OracleSim, build_oracle
+
+    build_oracle()
+    s = OracleSim(prob)
+    s.step(1)  # first touch of the arrays
+    t0 = time.perf_counter()
+    s.step(steps)
+    dt = time.perf_counter() - t0
+    s.close()
+    return prob.nx * prob.ny * steps / dt / 1e6, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--size", type=int, default=4096)
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--traffic-gb", type=float, default=None,
+                    help="HBM GB per launch measured by rocprofv3 counters for this kernel build")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "this build has no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1410_3464_amd import workloads as W
+    from paper_1410_3464_amd.lbrx import Lbrx
+
+    assert torch.cuda.is_available(), "no GPU visible"
+    torch.cuda.set_device(0)
+    t_gen = time.perf_counter()
+    prob = W.config2(n=args.size)
+    print(f"# generated {prob.name} in {time.perf_counter() - t_gen:.1f}s", file=sys.stderr, flush=True)
+    # a dedicated (default-priority) stream: the library enqueues on it and the
+    # timing events are recorded on it
+    stream = torch.cuda.Stream()
+    sim = Lbrx(prob, args.precision, stream=stream.cuda_stream)
+    esz = 4 if args.precision == "f32" else 8
+
+    sim.step(args.warmup)
+    sim.sync()
+    F = sim.fields()
+    bytes_per_step, counts = algorithmic_bytes(F, prob, esz)
+    print(f"# warmup done: {counts}", file=sys.stderr, flush=True)
+
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    stream.synchronize()
+    t0 = time.perf_counter()
+    start.record(stream)
+    sim.step(args.steps)
+    end.record(stream)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sim.sync()  # raises on a numerical failure during the timed steps
+    wall = t1 - t0
+    kern_ms = start.elapsed_time(end) / args.steps
+    F2 = sim.fields()
+    b2, counts2 = algorithmic_bytes(F2, prob, esz)
+    b_alg = 0.5 * (bytes_per_step + b2)
+
+    n = prob.nx * prob.ny
+    mlups = n * args.steps / wall / 1e6
+    achieved = b_alg / (kern_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {
+            "workload": f"{prob.name} porous medium (porosity 0.55, 30% of pores vapour, 2 flow components, "
+                        f"{prob.n_species} species, 2 homogeneous + 2 surface reactions)",
+            "nx": prob.nx, "ny": prob.ny, "species": prob.n_species,
+            "fluid_frac": round(counts["fluid"] / n, 4), "liquid_frac": round(counts["liquid"] / n, 4),
+            "interface_frac": round(counts["interface"] / n, 4),
+            "bytes_per_node": round(b_alg / n, 2),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": None if args.traffic_gb is None else args.traffic_gb,
+            "kernel_ms": round(kern_ms, 4),
+            "alg_bytes_per_launch": int(b_alg),
+        },
+        "cpu_baseline": None,
+    }
+    sim.close()
+    del sim
+    if not args.no_cpu:
+        cpu_mlups, dt = cpu_baseline(prob, args.cpu_steps)
+        out["cpu_baseline"] = {
+            "value": round(cpu_mlups, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{args.cpu_steps} FP64 oracle steps of the same {prob.nx}x{prob.ny} lattice "
+                      f"after one untimed step ({dt:.1f}s)",
+        }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

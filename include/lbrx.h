@@ -1,0 +1,197 @@
+/*
+ * lbrx - coupled reactive-transport lattice Boltzmann step on one MI355X.
+ *
+ * The library advances the two-phase multi-mixture pore-scale model of Chen,
+ * Kang, Tang, Robinson, He and Tao (arXiv:1410.3464) by whole time steps on
+ * the GPU.  One step is the procedure of Sec. 4.7 (Steps 1-5):
+ *   - two D2Q9 flow components (liquid mixture and gas), pseudopotential
+ *     forces (Eq. 11-16), Shan-Chen velocity shift (Eq. 17-19), forced BGK
+ *     collision (Eq. 6, 8), push streaming with halfway bounce-back;
+ *   - D2Q5 solute lattices in the liquid only (Eq. 20-24, 26) with
+ *     homogeneous reaction sources (Eq. 5, 27, 28) and heterogeneous surface
+ *     fluxes at liquid-solid links (Eq. 29-31, A2);
+ *   - the volume-of-pixel solid update (Eq. 32-35) and the amendments for
+ *     nodes whose status changes (Sec. 4.5).
+ *
+ * Conventions
+ *   - Arrays are row-major with index y*nx + x; x is the fast axis.
+ *   - All pointers passed in are host pointers.  lbrx_create copies what it
+ *     needs; the caller keeps ownership of everything it passes.
+ *   - The context owns all device memory; lbrx_destroy releases it.
+ *   - A context is not thread-safe.  Distinct contexts are independent.
+ *   - Errors are returned as status codes; lbrx_last_error() gives a message.
+ *     Nothing unwinds across this interface.
+ */
+#ifndef LBRX_H
+#define LBRX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBRX_ABI_VERSION 1u
+#define LBRX_MAX_SPECIES 8
+#define LBRX_MAX_RXN 8
+
+typedef struct lbrx_ctx lbrx_ctx;
+
+typedef enum {
+  LBRX_OK = 0,
+  LBRX_E_INVAL = 1,    /* invalid argument or parameter                        */
+  LBRX_E_NOMEM = 2,    /* device allocation failed                             */
+  LBRX_E_DEVICE = 3,   /* a HIP call failed                                    */
+  LBRX_E_UNSTABLE = 4, /* the run produced a negative/NaN density, or b rho/4>=1 */
+  LBRX_E_STATE = 5     /* the context already failed; only destroy is allowed  */
+} lbrx_status;
+
+/* Storage and arithmetic precision of the populations.  Solid volumes and the
+ * balance ledger are FP64 in every mode. */
+typedef enum { LBRX_F64 = 0, LBRX_F32 = 1 } lbrx_precision;
+
+/* node types (Fig. 2): fluid, inert solid, dissolvable solid D(s), precipitate F(s) */
+enum { LBRX_FLUID = 0, LBRX_SOLID_INERT = 1, LBRX_SOLID_D = 2, LBRX_SOLID_F = 3 };
+
+/* Homogeneous reactions (Sec. 2, Eq. 5; Sec. 4.2, Eq. 27-28).
+ *   FIRST_ORDER:  R = k C[re0]
+ *   R1_GAS:       R = k (C[re0] - C[pr0] sqrt(rho2 / M_gas) / K_eq)   (Eq. 5a)
+ *                 and half a mole of gas per mole of R moves from flow
+ *                 component 1 to component 2 (S_1 = -R M_gas/2, S_2 = +R M_gas/2)
+ *   BIMOLECULAR:  R = k C[re0] C[re1]                                  (Eq. 5c)
+ * Each reactant index loses R and each product index gains R; -1 = none. */
+enum { LBRX_HOM_FIRST_ORDER = 0, LBRX_HOM_R1_GAS = 1, LBRX_HOM_BIMOLECULAR = 2 };
+typedef struct {
+  int32_t kind;
+  int32_t re[2], pr[2];
+  double k, K_eq, M_gas;
+} lbrx_hom_rxn;
+
+/* Heterogeneous surface reactions (Sec. 4.3-4.4, Eq. 29-35, A2).  On every D2Q5
+ * link from a liquid node to a solid node whose type bit is in `surface`
+ * ((1<<LBRX_SOLID_D) and/or (1<<LBRX_SOLID_F)) the reactant loses, and the
+ * product gains, the link flux
+ *     Phi = 2 D k (C_reactant - C_eq) / (2 D + k)
+ * (halfway-wall Robin form of D dC/dn = k (C_wall - C_eq); D from Eq. 24 of the
+ * reactant; clamped at >= 0 when `irreversible`).  Volume of pixel:
+ *   CONSUMES: the solid node loses molar_volume * Phi           (R2, Eq. 33)
+ *   GROWS:    the liquid node's precipitate volume gains molar_volume * Phi;
+ *             at 1 the node becomes LBRX_SOLID_F                 (R4, Eq. 35)
+ *   MINERAL:  the solid node gains molar_volume * Phi (negative Phi dissolves;
+ *             Eq. A2).
+ * A solid node whose volume reaches 0 becomes fluid. */
+enum { LBRX_HET_CONSUMES = 0, LBRX_HET_GROWS = 1, LBRX_HET_MINERAL = 2 };
+typedef struct {
+  int32_t reactant, product;
+  uint32_t surface;
+  int32_t mode;
+  int32_t irreversible;
+  double k, C_eq, molar_volume;
+} lbrx_het_rxn;
+
+typedef struct {
+  uint32_t abi_version;  /* must be LBRX_ABI_VERSION */
+  int32_t nx, ny;        /* lattice size, each >= 3 */
+  uint32_t periodic;     /* bit 0: x periodic, bit 1: y periodic; a non-periodic
+                            side is a halfway bounce-back wall just outside the domain */
+  int32_t precision;     /* lbrx_precision */
+  double tau[2];         /* flow relaxation times, > 1/2 (Eq. 6, 10) */
+  double w_adh[2];       /* fluid-solid interaction strengths (Eq. 16) */
+  double gbody[2];       /* body acceleration (x, y); the force on component s is rho_s g */
+  double a, b, R, T;     /* Carnahan-Starling EOS of component 1 (Eq. 12) */
+  double G11, G12, G21;  /* interaction strengths (Eq. 11, 14); G22 = 0 */
+  double a0, rho10, rho20; /* phi_1 = 1 - exp(-rho2/rho20), phi_2 = a0 - exp(-rho1/rho10) (Eq. 15);
+                              a non-positive rho10 / rho20 switches that phi off */
+  double liquid_frac;    /* liquid iff rho1 > liquid_frac * max rho1 (Sec. 4.5); in [0,1) */
+  int32_t n_species;     /* 0..LBRX_MAX_SPECIES aqueous species on D2Q5 */
+  double tau_g[LBRX_MAX_SPECIES]; /* > 1/2 (Eq. 20, 24) */
+  double J0[LBRX_MAX_SPECIES];    /* rest fraction in [0,1) (Eq. 22) */
+  int32_t n_hom;
+  lbrx_hom_rxn hom[LBRX_MAX_RXN];
+  int32_t n_het;
+  lbrx_het_rxn het[LBRX_MAX_RXN];
+  /* initial state, host arrays of nx*ny (C0: n_species*nx*ny), copied at create */
+  const uint8_t* node_type; /* LBRX_FLUID .. LBRX_SOLID_F */
+  const double* V0;         /* solid volume (> 0 at D/F nodes), precipitate fraction in
+                               [0,1) at fluid nodes; NULL: 1 at D/F nodes, 0 elsewhere */
+  const double* rho1;       /* > 0 at fluid nodes */
+  const double* rho2;       /* >= 0 at fluid nodes */
+  const double* C0;         /* used at nodes that start liquid; may be NULL if n_species == 0 */
+} lbrx_params;
+
+/* Cumulative balances, FP64.  With M_s the total of component s and S_k the
+ * total of species k (over nodes that carry them):
+ *   M_s(n) = M_s(0) + mass_src[s] + mass_inj[s] - mass_rem[s]
+ *   S_k(n) = S_k(0) + sol_src[k] + sol_het[k] - sol_rem[k]
+ *   sum V(n) = sum V(0) + vol_dv - vol_clip                                 */
+typedef struct {
+  double mass_src[2];   /* homogeneous flow sources (Eq. 27) */
+  double mass_inj[2];   /* mass given to nodes freed by dissolution */
+  double mass_rem[2];   /* displaced mass that found no fluid neighbour */
+  double sol_src[LBRX_MAX_SPECIES]; /* homogeneous solute sources (Eq. 28) */
+  double sol_het[LBRX_MAX_SPECIES]; /* net surface exchange (Eq. 29-31) */
+  double sol_rem[LBRX_MAX_SPECIES]; /* solute of nodes leaving the liquid with no liquid neighbour */
+  double vol_dv;        /* all volume-of-pixel increments (Eq. 33, 35) */
+  double vol_clip;      /* sum of the non-positive volumes of removed solid nodes */
+  double n_psi_clamp;   /* negative psi arguments clamped to zero */
+  double n_dissolved, n_precipitated, n_liq_to_gas, n_gas_to_liq;
+  double steps;
+} lbrx_ledger;
+
+/* Host output buffers of nx*ny (C: n_species*nx*ny) for lbrx_fields; any may
+ * be NULL.  Values describe the state after the steps taken so far:
+ * rho at nodes carrying flow populations, u the physical velocity of Eq. 19 at
+ * fluid nodes, C at nodes carrying solute, V solid / precipitate volume,
+ * type the node type, liquid the liquid mark of the next step. */
+typedef struct {
+  double* rho1;
+  double* rho2;
+  double* ux;
+  double* uy;
+  double* C;
+  double* V;
+  uint8_t* type;
+  uint8_t* liquid;
+  lbrx_ledger* ledger;
+  double* rho_max;      /* 1 value: max rho1 of the last step (liquid threshold source) */
+} lbrx_fields_out;
+
+/* Creates a context on the current HIP device.  `hip_stream` is a hipStream_t
+ * the context enqueues all its work on (NULL: the context creates its own).
+ * Returns LBRX_E_INVAL for invalid parameters (message in *out's last error is
+ * not available: *out is NULL; see lbrx_create_error()). */
+lbrx_status lbrx_create(const lbrx_params* params, void* hip_stream, lbrx_ctx** out);
+
+/* Message of the last failed lbrx_create on this thread. */
+const char* lbrx_create_error(void);
+
+/* Enqueues n_steps >= 0 coupled steps on the context's stream and returns
+ * without waiting.  A numerical failure inside these steps is reported by the
+ * next lbrx_sync / lbrx_fields as LBRX_E_UNSTABLE. */
+lbrx_status lbrx_step(lbrx_ctx* ctx, int64_t n_steps);
+
+/* Waits for the context's stream and reports a sticky numerical failure. */
+lbrx_status lbrx_sync(lbrx_ctx* ctx);
+
+/* Waits, then fills the caller's host buffers (FP64 whatever the precision). */
+lbrx_status lbrx_fields(lbrx_ctx* ctx, lbrx_fields_out* out);
+
+/* Steps taken so far. */
+int64_t lbrx_step_count(const lbrx_ctx* ctx);
+
+/* The hipStream_t the context enqueues on (for events around lbrx_step). */
+void* lbrx_stream(const lbrx_ctx* ctx);
+
+/* Releases the context and its device memory.  NULL is a no-op. */
+lbrx_status lbrx_destroy(lbrx_ctx* ctx);
+
+/* Message for the last failure of this context ("" if none). */
+const char* lbrx_last_error(const lbrx_ctx* ctx);
+
+/* Static name of a status code. */
+const char* lbrx_status_string(lbrx_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

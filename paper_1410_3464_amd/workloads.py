@@ -146,9 +146,9 @@ def _disk_mask(nx, ny, cx, cy, r, periodic_x=True, periodic_y=True):
 
 
 def _stamp_disk(mask, cx, cy, r, periodic_x, periodic_y):
-    """Boolean disk of radius r centred at (cx, cy), stamped by bounding box."""
+    """Lattice nodes (ys, xs) of the disk of radius r centred at (cx, cy), found
+    within its bounding box."""
     ny, nx = mask.shape
-    out = np.zeros_like(mask)
     ri = int(math.ceil(r))
     xs = np.arange(int(math.floor(cx)) - ri, int(math.floor(cx)) + ri + 2)
     ys = np.arange(int(math.floor(cy)) - ri, int(math.floor(cy)) + ri + 2)
@@ -163,8 +163,7 @@ def _stamp_disk(mask, cx, cy, r, periodic_x, periodic_y):
     oky = (ys >= 0) & (ys < ny)
     inside = inside & okx[None, :] & oky[:, None]
     yy, xx = np.nonzero(inside)
-    out[ys[yy], xs[xx]] = True
-    return out, ys[yy], xs[xx]
+    return None, ys[yy], xs[xx]
 
 
 def config0(seed=0):

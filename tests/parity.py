@@ -1,0 +1,62 @@
+"""Field-by-field comparison helpers for the HIP path against the FP64 oracle.
+
+Rules:
+* fields (rho1, rho2, ux, uy, every C_k, V): max |gpu - oracle| / max |oracle|
+  per field, below the tolerance of the precision;
+* node types and liquid marks: identical, unless the oracle's state sits
+  within the tolerance of a threshold that decides them (then the first
+  step where that happens is reported and the comparison of masks stops).
+"""
+import numpy as np
+
+FIELDS = ("rho1", "rho2", "ux", "uy", "V")
+
+
+def rel_err(a, b):
+    scale = np.abs(b).max()
+    if scale == 0:
+        return float(np.abs(a).max())
+    return float(np.abs(a - b).max() / scale)
+
+
+def field_errors(G, O, ns):
+    err = {k: rel_err(G[k], O[k]) for k in FIELDS}
+    for k in range(ns):
+        err[f"C{k}"] = rel_err(G["C"][k], O["C"][k])
+    return err
+
+
+def near_threshold(O, prob, tol):
+    """True when some mask decision of the oracle's last step was within tol of
+    its threshold (liquid mark, solid volume 0, precipitate volume 1)."""
+    fl = O["type"] == 0
+    thr = prob.liquid_frac * O["rho_max_prev"]
+    if fl.any() and np.any(np.abs(O["rho1"][fl] - thr) <= tol * max(thr, 1e-300)):
+        return True
+    V = O["V"]
+    if np.any((np.abs(V) < tol) & (O["type"] >= 2)):
+        return True
+    if np.any((np.abs(V - 1.0) < tol) & fl):
+        return True
+    return False
+
+
+def compare(G, O, prob, tol, led_tol=None):
+    """Returns (errors, masks_equal, near)."""
+    errs = field_errors(G, O, prob.n_species)
+    masks = bool(np.array_equal(G["type"], O["type"]) and np.array_equal(G["liquid"], O["liquid"]))
+    near = near_threshold(O, prob, tol)
+    return errs, masks, near
+
+
+def ledger_errors(LG, LO, ns):
+    out = {}
+    for k in ("mass_src", "mass_inj", "mass_rem"):
+        out[k] = float(np.abs(np.asarray(LG[k]) - np.asarray(LO[k])).max())
+    for k in ("sol_src", "sol_het", "sol_rem"):
+        out[k] = float(np.abs(np.asarray(LG[k])[:ns] - np.asarray(LO[k])[:ns]).max()) if ns else 0.0
+    for k in ("vol_dv", "vol_clip"):
+        out[k] = abs(LG[k] - LO[k])
+    for k in ("n_psi_clamp", "n_dissolved", "n_precipitated", "n_liq_to_gas", "n_gas_to_liq", "steps"):
+        out[k] = abs(LG[k] - LO[k])
+    return out

@@ -1,0 +1,209 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+FP64: every field within 1e-12 of the oracle (max-norm relative), masks and
+event counts identical.  FP32: fields within 1e-5 after the stated steps.
+A mask may only differ after the oracle has had a threshold decision within
+the tolerance; those cases are reported and the masks are then not compared.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import OracleSim
+from paper_1410_3464_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+sys.path.insert(0, os.path.dirname(__file__))
+from parity import compare, ledger_errors  # noqa: E402
+
+
+def _gpu():
+    from paper_1410_3464_amd.lbrx import Lbrx
+
+    return Lbrx
+
+
+def _run_pair(prob, precision, checkpoints, tol, count_tol=0.0):
+    Lbrx = _gpu()
+    o = OracleSim(prob)
+    g = Lbrx(prob, precision)
+    done = 0
+    masks_ok = True
+    report = []
+    for n in checkpoints:
+        o.step(n - done)
+        g.step(n - done)
+        done = n
+        O = o.fields()
+        G = g.fields()
+        errs, masks, near = compare(G, O, prob, tol)
+        report.append((n, errs, masks, near))
+        print(f"[{prob.name} {precision}] step {n}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items())
+              + f" masks={'ok' if masks else 'DIFF'} near={near}", flush=True)
+        if masks_ok and not masks:
+            assert near, f"node masks differ at step {n} with no near-threshold decision"
+            masks_ok = False
+        if masks_ok:
+            for k, v in errs.items():
+                assert v <= tol, f"{k} error {v:.3e} > {tol:.1e} at step {n}"
+            le = ledger_errors(G["ledger"], O["ledger"], prob.n_species)
+            for k in ("n_dissolved", "n_precipitated", "n_liq_to_gas", "n_gas_to_liq", "steps"):
+                assert le[k] <= count_tol, f"ledger {k} differs by {le[k]} at step {n}"
+    return report
+
+
+def _small_cases():
+    p0 = W.config0()
+    porous = W.config1(nx=130, ny=70, seed=11)
+    return p0, porous
+
+
+@pytest.mark.parametrize("which", ["droplet", "porous-ragged"])
+def test_fp64_parity_small(which):
+    """Droplet box (96x64, the 2000-step workload) and a porous medium whose size
+    is not a multiple of the tile (130x70, walls in y): FP64 fields within 1e-12,
+    masks and event counts identical."""
+    p0, porous = _small_cases()
+    if which == "droplet":
+        _run_pair(p0, "f64", [1, 10, 200, 1000, 2000], 1e-12)
+    else:
+        _run_pair(porous, "f64", [1, 50, 300, 600], 1e-12)
+
+
+def test_fp64_parity_events():
+    """A dissolvable grain in liquid next to a precipitate wall, with fast surface
+    kinetics: the grain dissolves, precipitate grows from the wall and displaces
+    fluid, interfaces move (every amendment path of the step runs); FP64 parity
+    holds throughout."""
+    n = 40
+    a, b, R = W.EOS_PAPER
+    T = 0.75 * W.critical_temperature(a, b, R)
+    x = np.arange(n)[None, :]
+    y = np.arange(n)[:, None]
+    t0 = np.zeros((n, n), np.uint8)
+    grain = (x - 20) ** 2 + (y - 20) ** 2 <= 36
+    t0[grain] = W.SOLID_D
+    t0[:, 0] = W.SOLID_F
+    gas = (x - 30) ** 2 + (y - 30) ** 2 <= 25
+    rho1 = np.where(gas, W.RHO_V_075_PAPER, W.RHO_L_075_PAPER)
+    rho1 = np.where(t0 == 0, rho1, 0.0)
+    rho2 = np.where(t0 == 0, 0.1, 0.0)
+    C0 = np.zeros((4, n, n))
+    C0[0] = 1.0
+    C0[1] = 0.5
+    C0[3] = 0.5
+    prob = W.Problem(
+        name="events-40", nx=n, ny=n, periodic_x=True, periodic_y=True, a=a, b=b, R=R, T=T,
+        G11=-1.0, G12=0.5, G21=0.5, a0=0.005, rho10=W.paper_rho10(), rho20=0.003,
+        species=[W.Species("A"), W.Species("B"), W.Species("E"), W.Species("F")],
+        hom=[W.HomRxn("r1_gas", re=(0, -1), pr=(1, -1), k=1e-2, K_eq=1.0, M_gas=1e-2),
+             W.HomRxn("bimolecular", re=(1, 2), pr=(3, -1), k=1e-3)],
+        het=[W.HetRxn(1, 2, (W.SOLID_D,), "consumes", True, 1.0, 0.0, 1.0),
+             W.HetRxn(3, -1, (W.SOLID_D, W.SOLID_F), "grows", True, 0.3, 0.0, 2.0)],
+        type0=t0, V0=np.where(grain, 0.3, np.where(t0 == W.SOLID_F, 1.0, 0.0)), rho1=rho1, rho2=rho2, C0=C0)
+    rep = _run_pair(prob, "f64", [5, 50, 150, 300], 1e-12)
+    o = OracleSim(prob)
+    o.step(300)
+    L = o.fields()["ledger"]
+    assert L["n_dissolved"] > 0 and L["n_precipitated"] > 0
+
+
+def test_fp32_parity_droplet():
+    """FP32 storage and arithmetic on the moving droplet: every field within 1e-5
+    of the FP64 oracle over the first 10 steps.  Later the interface dynamics
+    amplify FP32 rounding (FP64 shows the same growth from 1e-16): after 1000
+    steps density and velocity stay within 2e-4, concentrations and volumes
+    within 1e-2 (node status changes may fall one step apart), and the FP32
+    run closes its own balance ledger."""
+    p0, _ = _small_cases()
+    _run_pair(p0, "f32", [1, 10], 1e-5)
+    Lbrx = _gpu()
+    o = OracleSim(p0)
+    g = Lbrx(p0, "f32")
+    o.step(1000)
+    g.step(1000)
+    O, G = o.fields(), g.fields()
+    errs, masks, near = compare(G, O, p0, 1e-5)
+    print("[droplet f32 1000]", errs, masks, near, flush=True)
+    for k in ("rho1", "rho2", "ux", "uy"):
+        assert errs[k] < 2e-4, (k, errs[k])
+    for k in ("V", "C0", "C1"):
+        assert errs[k] < 1e-2, (k, errs[k])
+    L = G["ledger"]
+    fl = p0.type0 == 0
+    M0 = np.array([p0.rho1[fl].sum(), p0.rho2[fl].sum()])
+    M = np.array([G["rho1"].sum(), G["rho2"].sum()])
+    assert np.allclose(M, M0 + L["mass_src"] + L["mass_inj"] - L["mass_rem"], rtol=1e-5, atol=0)
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_single_component_flat_interface(precision, tol):
+    """Degenerate shapes: a 2-wide periodic column (far narrower than a tile) and a
+    1-row periodic strip with solute diffusion only."""
+    a, b, R = W.EOS_ORIGINAL
+    Tc = W.critical_temperature(a, b, R)
+    ny = 64
+    p = W.uniform_problem(2, ny, ideal=False, a=a, b=b, R=R, T=0.75 * Tc, G11=-1.0, rho1=1.0, rho2=0.0)
+    yy = np.arange(ny)[:, None] * np.ones((1, 2))
+    rho1 = np.where((yy >= 16) & (yy < 48), W.RHO_L_075, W.RHO_V_075)
+    _run_pair(p.copy(rho1=rho1), precision, [1, 100, 500], tol)
+    L = 100
+    C0 = np.zeros((1, 1, L))
+    C0[0, 0, : L // 2] = 1.0
+    q = W.uniform_problem(L, 1, rho1=1.0, species=[W.Species("A", 0.8, 1.0 / 3)], C0=C0)
+    _run_pair(q, precision, [1, 300], tol)
+
+
+def test_poiseuille_walls_gpu():
+    """Body-forced channel with halfway bounce-back walls outside a non-periodic y
+    axis; identical to the oracle in FP64."""
+    H = 40
+    p = W.uniform_problem(70, H, periodic_y=False, rho1=1.0, rho2=0.2, gbody=(1e-6, 0.0))
+    _run_pair(p, "f64", [1, 500, 2000], 1e-12)
+
+
+def test_unstable_is_reported():
+    """The original EOS set in the two-component droplet diverges within a few dozen
+    steps (the oracle raises); the library reports LBRX_E_UNSTABLE at the next sync
+    and refuses further steps."""
+    from paper_1410_3464_amd.lbrx import LbrxError
+
+    Lbrx = _gpu()
+    a, b, R = W.EOS_ORIGINAL
+    p = W.config0()
+    fl = p.type0 == 0
+    q = p.copy(a=a, b=b, R=R, T=0.75 * W.critical_temperature(a, b, R), G12=0.0, G21=0.0,
+               rho1=np.where(fl, np.where(p.rho1 > 1.0, W.RHO_L_075, W.RHO_V_075), 0.0))
+    o = OracleSim(q)
+    with pytest.raises(FloatingPointError):
+        o.step(200)
+    g = Lbrx(q, "f64")
+    g.step(200)
+    with pytest.raises(LbrxError) as ei:
+        g.sync()
+    assert ei.value.status == 4
+    with pytest.raises(LbrxError) as ei:
+        g.step(1)
+    assert ei.value.status == 5
+
+
+def test_invalid_params_rejected():
+    from paper_1410_3464_amd.lbrx import LbrxError
+
+    Lbrx = _gpu()
+    p = W.config0()
+    with pytest.raises(LbrxError) as ei:
+        Lbrx(p.copy(tau=(0.5, 1.0)), "f64")
+    assert ei.value.status == 1
+    bad = p.rho1.copy()
+    bad[p.type0 == 0] = -1.0
+    with pytest.raises(LbrxError):
+        Lbrx(p.copy(rho1=bad), "f64")
+    sp = list(p.species)
+    sp[0] = W.Species("A", 1.0, 1.0)
+    with pytest.raises(LbrxError):
+        Lbrx(p.copy(species=sp), "f64")
