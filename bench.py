@@ -82,6 +82,8 @@ def main():
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe-gb", type=float, default=0.0,
+                    help="run a plain device-to-device copy of this many GB first (counter calibration)")
     ap.add_argument("--traffic-gb", type=float, default=None,
                     help="HBM GB per launch measured by rocprofv3 counters for this kernel build")
     args = ap.parse_args()
@@ -99,6 +101,14 @@ def main():
 
     assert torch.cuda.is_available(), "no GPU visible"
     torch.cuda.set_device(0)
+    if args.copy_probe_gb > 0:
+        n_el = int(args.copy_probe_gb * 1e9) // 4
+        src = torch.ones(n_el, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# copy probe: {n_el * 4} bytes read and written", file=sys.stderr, flush=True)
+        del src, dst
     t_gen = time.perf_counter()
     prob = W.config2(n=args.size)
     print(f"# generated {prob.name} in {time.perf_counter() - t_gen:.1f}s", file=sys.stderr, flush=True)

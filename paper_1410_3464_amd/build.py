@@ -14,10 +14,13 @@ LIB = os.path.join(HERE, "liblbrx.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -ffp-contract=off keeps the FP64 path's rounding identical to a plain
-# evaluation of the same expressions; packed FP32 instructions are disabled.
+# evaluation of the same expressions; FP32 division and square root use the
+# hardware's approximate instructions (FP64 stays IEEE); packed FP32
+# instructions are disabled.
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-    "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-ffp-contract=off", "-fno-hip-fp32-correctly-rounded-divide-sqrt",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
 ]
 

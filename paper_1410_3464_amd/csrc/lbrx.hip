@@ -4,25 +4,30 @@
 // Method: arXiv:1410.3464, Sec. 3-4 (Eq. 6-35, A2), procedure of Sec. 4.7.
 //
 // Kernel structure (one launch per time step):
-//   * A workgroup owns a 62 x TY tile of nodes and runs one thread per node of
-//     the tile plus a one-node ring (64 x (TY+2) threads, one wavefront per row).
-//   * Phase 1: every thread reads its node's streamed populations (SoA, push
-//     layout, coalesced along x), forms the moments (Eq. 9, 23) and the
-//     effective masses psi_1, phi_1, phi_2 (Eq. 13, 15) and stages them in LDS.
-//     Node types of the tile plus two rings go to LDS as bytes.
-//   * Phase 2: tile threads form the forces (Eq. 11, 14, 16) from the LDS
-//     stencil, the velocities (Eq. 17-19), reaction sources (Eq. 5, 27, 28),
-//     both collisions (Eq. 6, 20), the status-change amendments (Sec. 4.5),
-//     the volume-of-pixel update (Eq. 33, 35) and push-stream their
-//     populations with halfway bounce-back and the reactive link flux.
+//   * State between steps: post-collision populations f*, g* of every node in
+//     its own slots (row-interleaved structure of arrays: population q of row
+//     y at (y * NP + q) * pitch + x), one 32-bit status word per node (type,
+//     liquid marks, and which neighbours were fluid / liquid when the
+//     populations were written), the FP64 solid / precipitate volume.
+//   * One wavefront owns a 64-column by H-row item and marches down it.  Per
+//     row it pulls the next row's populations along the links (halfway
+//     bounce-back where the status word names no fluid neighbour), forms the
+//     moments (Eq. 9, 23) and effective masses psi_1, phi_1, phi_2 (Eq. 13,
+//     15) into a three-row LDS ring, then for the current row forms the forces
+//     (Eq. 11, 14, 16) from the ring, the velocities (Eq. 17-19), reaction
+//     sources (Eq. 5, 27, 28), both collisions (Eq. 6, 20), the status-change
+//     amendments (Sec. 4.5), the volume-of-pixel update (Eq. 33, 35) and the
+//     reactive link flux (Eq. 29-31, A2), and stores the results in place.
 //   * Nothing is read back in the same launch, so there is no grid-wide sync;
 //     the liquid threshold uses the previous step's maximum (atomic max on the
 //     bit pattern of a non-negative double), and balances accumulate into one
-//     FP64 record per tile (no floating-point atomics in global memory).
+//     FP64 record per item (no floating-point atomics in global memory).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 #include <cstdint>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -44,14 +49,18 @@ __host__ __device__ constexpr double wf(int a) { return a == 0 ? 0.0 : (a < 5 ? 
 static_assert(opp(1) == 3 && opp(2) == 4 && opp(3) == 1 && opp(4) == 2, "opp axes");
 static_assert(opp(5) == 7 && opp(6) == 8 && opp(7) == 5 && opp(8) == 6, "opp diagonals");
 
-// node-type byte: bits 0-1 type, bit 2 liquid this step, bit 3 liquid last
-// step, bit 4 stranded (became SOLID_F at the end of the last step; its
-// streamed-in populations are still stored).  Bit 7 marks "outside a
-// non-periodic boundary" in LDS only.
-constexpr uint8_t TB_T = 0x3, TB_LIQ = 0x4, TB_LIQP = 0x8, TB_STR = 0x10, TB_WALL = 0x80;
+// Node status word (32 bits): bits 0-1 type, bit 2 liquid this step, bit 3
+// liquid last step, bit 4 stranded (became SOLID_F at the end of the last step;
+// its incoming populations are still to be pulled and given away), bits 8-15
+// neighbour b = 1..8 was fluid last step, bits 16-19 D2Q5 neighbour b = 1..4 was
+// liquid last step.  A node with none of bits 8-19 set reads its own slots
+// back; that is how the initial state and a node freed by dissolution (both
+// at rest, whose populations are equal in opposite directions) enter the pull.
+// Bit 7 marks "outside a non-periodic boundary" in the kernel only.
+constexpr uint32_t TB_T = 0x3, TB_LIQ = 0x4, TB_LIQP = 0x8, TB_STR = 0x10, TB_WALL = 0x80;
+constexpr int NBF_SHIFT = 8, NBL_SHIFT = 16;
 constexpr int T_FLUID = 0, T_INERT = 1, T_D = 2, T_F = 3;
 
-constexpr int TW = 62;  // tile width: a 64-lane row minus the two ring lanes
 
 // ledger slots, same order as lbrx_ledger
 constexpr int L_MSRC = 0, L_MINJ = 2, L_MREM = 4, L_SSRC = 6, L_SHET = 14, L_SREM = 22, L_VDV = 30,
@@ -65,11 +74,19 @@ __host__ __device__ constexpr int rare_dst(int i) {
        : i == 5 ? L_CLAMP : i == 6 ? L_NDIS : i == 7 ? L_NPRE : i < 16 ? L_SREM + (i - 8) : i == 16 ? L_NL2G : L_NG2L;
 }
 
+// rho_max slots: 3 rotating step slots x 8 partial maxima (one per XCD), each
+// partial on its own 128-byte line so that workgroups on different XCDs never
+// contend for one address
+constexpr int RM_STRIDE = 16;  // u64 per partial
+constexpr int RM_SLOT = 8 * RM_STRIDE;
+constexpr int RM_WORDS = 3 * RM_SLOT;
+
 enum { HOM_FIRST = 0, HOM_R1 = 1, HOM_BI = 2 };
 enum { HET_CONSUMES = 0, HET_GROWS = 1, HET_MINERAL = 2 };
 
 struct KConst {
-  int nx, ny, pitch, per_x, per_y, tiles_x, tiles_y, nblocks, ns;
+  int nx, ny, pitch, per_x, per_y, strips, seg_rows, nitems, nblocks, ns;
+  unsigned fbytes, gbytes, tbytes;  // array sizes (buffer ranges)
   long long plane;
   double om[2], tau[2], RT, a, b, G11, psi_pre, G12, G21, w1, w2, gx, gy, a0, rho10, rho20, lfrac;
   int has_psi, has_phi1, has_phi2;
@@ -83,18 +100,31 @@ struct KConst {
   double xkap[LBRX_MAX_RXN], xCeq[LBRX_MAX_RXN], xmvol[LBRX_MAX_RXN];
 };
 
-struct KArgs {
+// Per-precision copies of the real constants (and reciprocals, used by the FP32
+// path in place of divisions by constants).
+template <typename T> struct KT {
+  T om[2], tau[2], r_tau[2], RT, a, b, G11, r_G11, psi_pre, G12, G21, w1, w2, gx, gy, a0, rho10, r_rho10,
+      rho20, r_rho20;
+  T J[LBRX_MAX_SPECIES][5];
+  T omg[LBRX_MAX_SPECIES];
+  T hk[LBRX_MAX_RXN], hKeq[LBRX_MAX_RXN], r_hKeq[LBRX_MAX_RXN], hMgas[LBRX_MAX_RXN], r_hMgas[LBRX_MAX_RXN];
+  T xkap[LBRX_MAX_RXN], xCeq[LBRX_MAX_RXN];
+  T hnu[LBRX_MAX_RXN][LBRX_MAX_SPECIES];  // net stoichiometric coefficient of species k in reaction r
+};
+
+template <typename T> struct KArgs {
   KConst c;
+  KT<T> k;
   const void* f_in;
   void* f_out;
   const void* g_in;
   void* g_out;
-  const uint8_t* t_in;
-  uint8_t* t_out;
+  const uint32_t* t_in;
+  uint32_t* t_out;
   double* V;
   unsigned long long* rmax;  // 3 rotating slots
   int slot_prev, slot_cur, slot_next;
-  double* led;               // [nblocks][NLED]
+  double* led;               // [nitems][NLED]
   unsigned int* err;         // [0] flags, [1] first failing node (min index)
   double *o_r1, *o_r2, *o_ux, *o_uy, *o_C;  // export outputs (plane-sized)
 };
@@ -111,10 +141,28 @@ __device__ inline bool wrap(int& X, int n, int per) {
 
 template <typename T> __device__ inline T dexp(T x);
 template <> __device__ inline double dexp<double>(double x) { return exp(x); }
-template <> __device__ inline float dexp<float>(float x) { return expf(x); }
+template <> __device__ inline float dexp<float>(float x) { return __expf(x); }
 template <typename T> __device__ inline T dsqrt(T x);
 template <> __device__ inline double dsqrt<double>(double x) { return sqrt(x); }
 template <> __device__ inline float dsqrt<float>(float x) { return sqrtf(x); }
+
+// a / b: IEEE division in FP64 (same rounding as the plain expression); in FP32
+// the hardware reciprocal (1 ulp) times a.
+template <typename T> __device__ inline T qdiv(T a, T b);
+template <> __device__ inline double qdiv<double>(double a, double b) { return a / b; }
+template <> __device__ inline float qdiv<float>(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+// a / c for a constant c with precomputed reciprocal rc
+template <typename T> __device__ inline T cdiv(T a, T c, T rc);
+template <> __device__ inline double cdiv<double>(double a, double c, double) { return a / c; }
+template <> __device__ inline float cdiv<float>(float a, float, float rc) { return a * rc; }
+
+// loads and stores at a uniform base plus a 32-bit byte offset
+template <typename T> __device__ inline T ldb(const T* base, unsigned off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
+}
+template <typename T> __device__ inline void stb(T* base, unsigned off, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off) = v;
+}
 
 template <int NS, typename T> __device__ inline T sel(const T (&v)[NS > 0 ? NS : 1], int i) {
   T r = T(0);
@@ -129,577 +177,896 @@ template <int NS, typename T> __device__ inline void addto(T (&v)[NS > 0 ? NS : 
     if (k == i) v[k] += x;
 }
 
-__device__ inline double wave_sum(double v) {
+// Wave (64-lane) reductions; a wave whose values are all zero skips the shuffles.
+template <typename T> __device__ inline T wave_sum_t(T v) {
+  if (__ballot(v != T(0)) == 0ull) return T(0);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
-__device__ inline double wave_max(double v) {
+template <typename T> __device__ inline T wave_max_t(T v) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  for (int o = 32; o > 0; o >>= 1) {
+    const T w = __shfl_xor(v, o, 64);
+    v = w > v ? w : v;
+  }
   return v;
 }
 
 // Carnahan-Starling pressure (Eq. 12), same operation order as the text.
-template <typename T> __device__ inline T p_cs(const KConst& c, T rho) {
-  const T e = T(0.25) * T(c.b) * rho;
+template <typename T> __device__ inline T p_cs(const KT<T>& k, T rho) {
+  const T e = T(0.25) * k.b * rho;
   const T om = T(1) - e;
   const T num = T(1) + e + e * e - e * e * e;
-  return rho * T(c.RT) * num / (om * om * om) - T(c.a) * rho * rho;
+  return qdiv<T>(rho * k.RT * num, om * om * om) - k.a * rho * rho;
 }
 
 // ---------------------------------------------------------------- step kernel
-template <typename T, int NS, int TY, bool EXPORT>
-__global__ __launch_bounds__(64 * (TY + 2)) void k_step(const KArgs A) {
-  constexpr int BY = TY + 2;
-  constexpr int NSA = NS > 0 ? NS : 1;
-  const KConst& c = A.c;
-  __shared__ uint8_t s_t[TY + 4][68];
-  __shared__ T s_r1[BY][64], s_r2[BY][64], s_ps[BY][64], s_q1[BY][64], s_q2[BY][64];
-  __shared__ T s_C[NSA][BY][64];
-  __shared__ double s_red[BY][4 + 2 * NSA];
-  __shared__ double s_rare[NRARE_SLOTS];
-  __shared__ double s_rmax[BY];
+// One launch = one time step n.  Populations are stored after collision
+// (f*(n-1), g*(n-1)) in the slots of the node that produced them; the kernel
+// first pulls them along the lattice links (the streaming of step n-1, with
+// halfway bounce-back against the previous step's masks, which each node keeps
+// in its status word), then runs step n and writes f*(n), g*(n) back into the
+// node's own slots.  Own-slot stores let every written 128-byte line be
+// complete: every lane of a 32-lane group that holds a valid population
+// stores (lanes without one store values that are never read).
+//
+// Work decomposition: one wavefront per item of SW = 64 columns (aligned to
+// the row pitch) by H rows.  The wavefront first computes the moments and
+// effective masses of the two halo columns (x0 - 1, x0 + 64) for its H + 2
+// rows in one pass, then marches down its rows: at row R it pulls row R + 1,
+// stages that row's psi, phi, node flags, densities and concentrations in a
+// three-row LDS ring, and collides row R against the ring.  Wavefronts never
+// wait for each other, so one wavefront's loads overlap another's arithmetic.
+//
+// Memory access is through raw buffer descriptors: a per-lane 32-bit offset
+// (one per link direction, shared by both components and all species) plus a
+// uniform offset for the population plane.
+constexpr int SW = 64;    // item width: one lane per column
+constexpr int HMAX = 30;  // most rows per item: both halo columns (H + 2 rows each) fit one wavefront
+// wavefronts per workgroup, each with its own item
+#ifndef LBRX_WPB
+#define LBRX_WPB 1
+#endif
+constexpr int WPB = LBRX_WPB;
+// lower bound on resident wavefronts per SIMD asked of the FP32 register
+// allocator (0: the compiler's choice)
+#ifndef LBRX_F32_WAVES
+#define LBRX_F32_WAVES 0
+#endif
+template <typename T> constexpr int min_waves() {
+  return (std::is_same<T, float>::value && LBRX_F32_WAVES > 0) ? LBRX_F32_WAVES : 1;
+}
 
-  // XCD-aware tile order: consecutive workgroups are dealt round-robin to the
-  // 8 XCDs; give each XCD a contiguous band of tiles so that the halo rows two
-  // neighbouring tiles share sit in the same L2.
-  const int nb = c.nblocks;
+// node flags as staged in LDS: status bits 0-4 of the word, plus
+constexpr uint32_t LF_LIQN = 0x20;  // liquid at this step (in the domain)
+constexpr uint32_t LF_FLU = 0x40;   // fluid at this step (in the domain)
+// (TB_WALL = 0x80: outside a non-periodic side)
+
+template <typename T> struct alignas(4 * sizeof(T)) PQ {
+  T ps, q1, q2, fl;  // psi_1, phi_1, phi_2 (zero at non-fluid nodes), node flags (bit pattern)
+};
+template <typename T> __device__ inline T flags_as(uint32_t v) {
+  if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, v);
+  else return __builtin_bit_cast(T, (unsigned long long)v);
+}
+template <typename T> __device__ inline uint32_t flags_of(T v) {
+  if constexpr (sizeof(T) == 4) return __builtin_bit_cast(uint32_t, v);
+  else return (uint32_t)__builtin_bit_cast(unsigned long long, v);
+}
+
+template <typename T, int NS> struct WaveLds {
+  static constexpr int NSA = NS > 0 ? NS : 1;
+  // ring rows (R - 1, R, R + 1 in rotation) x columns x0 - 1 .. x0 + 64
+  PQ<T> pq[3][SW + 2];
+  T r1[3][SW + 2], r2[3][SW + 2];
+  T C[NSA][3][SW + 2];
+  // halo columns (left, right) for rows y0 - 1 .. y0 + H
+  PQ<T> hpq[2][HMAX + 2];
+  T hr1[2][HMAX + 2], hr2[2][HMAX + 2];
+  T hC[NSA][2][HMAX + 2];
+  double rare[NRARE_SLOTS];
+};
+
+typedef unsigned int v2u_t __attribute__((ext_vector_type(2)));
+__device__ inline __amdgpu_buffer_rsrc_t rsrc_of(const void* p, unsigned bytes) {
+  // raw buffer: stride 0, a byte range, 32-bit data format in word 3
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T> __device__ inline T bload(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+  if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0));
+  else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0));
+}
+template <typename T> __device__ inline void bstore(T v, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+  if constexpr (sizeof(T) == 4) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)vo, (int)so, 0);
+  else __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u_t, v), r, (int)vo, (int)so, 0);
+}
+
+template <typename T, int NS> struct Mom {
+  T rho[2], jx[2], jy[2], C[NS > 0 ? NS : 1];
+};
+
+template <typename T, int NS, bool EXPORT>
+__global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const KArgs<T> A_arg) {
+  // The arguments are read where the launch put them (the kernarg segment, a
+  // constant address space): the helpers below refer to them, and a reference
+  // to the by-value parameter itself would make the compiler copy the whole
+  // block to private memory first.
+  (void)A_arg;
+  const KArgs<T>& A = *(const KArgs<T>*)__builtin_amdgcn_kernarg_segment_ptr();
+  constexpr int NSA = NS > 0 ? NS : 1;
+  constexpr unsigned ES = sizeof(T);
+  constexpr unsigned NPG = 5 * NS;
+  const KConst& c = A.c;
+  const KT<T>& k = A.k;
+  __shared__ WaveLds<T, NS> s_all[WPB];
+  WaveLds<T, NS>& L = s_all[threadIdx.y];
+  const int lane = threadIdx.x;
+
+  // XCD-aware order: consecutive workgroups are dealt round-robin to the 8
+  // XCDs; each XCD gets a contiguous band of items, so that the halo rows two
+  // vertically neighbouring items share sit in the same L2.
+  const int nb = gridDim.x;
   const int bid = blockIdx.x;
   const int xcd = bid & 7, loc = bid >> 3;
-  const int tile = xcd * (nb >> 3) + min(xcd, nb & 7) + loc;
-  const int tyi = tile / c.tiles_x, txi = tile - tyi * c.tiles_x;
-  const int x0 = txi * TW, y0 = tyi * TY;
-  const int tx = threadIdx.x, ty = threadIdx.y;
-  const int nx = c.nx, ny = c.ny, pitch = c.pitch;
-  const long long plane = c.plane;
+  const int blk = xcd * (nb >> 3) + min(xcd, nb & 7) + loc;
+  const int item = blk * WPB + (int)threadIdx.y;
+  if (item >= c.nitems) return;  // whole wavefront
+  const int sx = item % c.strips, sy = item / c.strips;
+  const int x0 = sx * SW, y0 = sy * c.seg_rows;
+  const int y1 = min(y0 + c.seg_rows, c.ny);
+  const int nrow = y1 - y0;
+  const int nx = c.nx, ny = c.ny;
+  const unsigned upitch = (unsigned)c.pitch;
+  const unsigned PS = upitch * ES;     // bytes per population plane row
+  const unsigned RSF = 18u * PS;       // bytes per lattice row, flow populations
+  const unsigned RSG = NPG * PS;       // bytes per lattice row, solute populations
 
-  if (!EXPORT && ty == 0 && tx < NRARE_SLOTS) s_rare[tx] = 0.0;
-  for (int k = ty * 64 + tx; k < (TY + 4) * 68; k += 64 * BY) {
-    const int j = k / 68, i = k - j * 68;
-    int X = x0 - 2 + i, Y = y0 - 2 + j;
-    uint8_t v = TB_WALL;
-    if (wrap(X, nx, c.per_x) && wrap(Y, ny, c.per_y)) v = A.t_in[(long long)Y * pitch + X];
-    s_t[j][i] = v;
-  }
+  const __amdgpu_buffer_rsrc_t rf = rsrc_of(A.f_in, c.fbytes);
+  const __amdgpu_buffer_rsrc_t rg = rsrc_of(A.g_in, c.gbytes);
+  const __amdgpu_buffer_rsrc_t rt = rsrc_of(A.t_in, c.tbytes);
 
-  // ------------------------------------------------------------ phase 1
-  const int X = x0 - 1 + tx, Y = y0 - 1 + ty;
-  const bool own = tx >= 1 && tx <= TW && ty >= 1 && ty <= TY && X < nx && Y < ny;
-  int Xw = X, Yw = Y;
-  const bool indom = wrap(Xw, nx, c.per_x) && wrap(Yw, ny, c.per_y);
-  const long long idx = (long long)Yw * pitch + Xw;
-  const uint8_t tb = indom ? A.t_in[idx] : TB_WALL;
-  const int t = tb & TB_T;
-  const bool fluid = indom && t == T_FLUID;
-  const bool validf = indom && (t == T_FLUID || (tb & TB_STR));
-  const bool liq = indom && (tb & TB_LIQ);
-  const bool liqp = indom && (tb & TB_LIQP);
+  if (!EXPORT && lane < NRARE_SLOTS) L.rare[lane] = 0.0;
 
-  const T* fi = static_cast<const T*>(A.f_in);
-  const T* gi = static_cast<const T*>(A.g_in);
-  T f[2][9];
-  T g[NSA][5];
-  T rho[2] = {T(0), T(0)}, jx[2] = {T(0), T(0)}, jy[2] = {T(0), T(0)};
-  T Ck[NSA];
+  auto is_fluid = [](uint32_t v) { return (v & LF_FLU) != 0; };
+  auto is_liq = [](uint32_t v) { return (v & LF_LIQN) != 0; };
+  auto is_rsolid = [](uint32_t v) { return !(v & TB_WALL) && (v & TB_T) >= T_D; };
+  // LDS flags of an in-domain node's status word
+  auto flags_w = [](uint32_t w) -> uint32_t {
+    return (w & 0x1fu) | ((w & TB_T) == T_FLUID ? LF_FLU : 0u) | (((w & TB_T) == T_FLUID && (w & TB_LIQ)) ? LF_LIQN : 0u);
+  };
+
+  // status word of node (X, Y), TB_WALL outside a non-periodic side
+  auto word_at = [&](int X, int Y) -> uint32_t {
+    if (wrap(X, nx, c.per_x) && wrap(Y, ny, c.per_y)) return bload<uint32_t>(rt, (unsigned)X * 4u, (unsigned)Y * upitch * 4u);
+    return TB_WALL;
+  };
+
+  // Pull (streaming of the previous step): population a arrives from
+  // x - e_a = x + e_b (b = opp(a)) if that node was fluid (liquid) then,
+  // otherwise it is this node's own population b bounced back at the halfway
+  // wall.  co[] are the byte offsets of columns x-1, x, x+1 (wrapped); Yw is
+  // the wrapped row of an in-domain node.
+  auto pull = [&](const unsigned (&co)[3], int Yw, uint32_t w, bool validf, bool liqp, T(&f)[2][9], T(&g)[NSA][5]) {
+    int ym = Yw - 1, yp = Yw + 1;
+    if (ym < 0) ym += ny;
+    if (yp >= ny) yp -= ny;
+    const unsigned ur[3] = {(unsigned)ym, (unsigned)Yw, (unsigned)yp};
+    if (validf) {
+      const unsigned own = co[1] + ur[1] * RSF;
+      f[0][0] = bload<T>(rf, own, 0);
+      f[1][0] = bload<T>(rf, own, 9 * PS);
 #pragma unroll
-  for (int s = 0; s < 2; ++s) {
+      for (int b = 1; b < 9; ++b) {
+        const int a = opp(b);
+        const bool src = (w >> (NBF_SHIFT + b - 1)) & 1u;
+        const unsigned vo = src ? co[ex(b) + 1] + (ur[ey(b) + 1] * RSF + (unsigned)a * PS) : own + (unsigned)b * PS;
+        const unsigned pa = src ? (unsigned)a : (unsigned)b;
+        (void)pa;
+        f[0][a] = bload<T>(rf, vo, 0);
+        f[1][a] = bload<T>(rf, vo, 9 * PS);
+      }
+    } else {
 #pragma unroll
-    for (int a = 0; a < 9; ++a) f[s][a] = validf ? fi[(s * 9 + a) * plane + idx] : T(0);
-  }
-  if (validf) {
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int a = 0; a < 9; ++a) f[s][a] = T(0);
+    }
+    if (NS > 0 && liqp) {
+      const unsigned own = co[1] + ur[1] * RSG;
+#pragma unroll
+      for (int kk = 0; kk < NS; ++kk) g[kk][0] = bload<T>(rg, own, (unsigned)(kk * 5) * PS);
+#pragma unroll
+      for (int b = 1; b < 5; ++b) {
+        const int a = opp(b);
+        const bool src = (w >> (NBL_SHIFT + b - 1)) & 1u;
+        const unsigned vo = src ? co[ex(b) + 1] + (ur[ey(b) + 1] * RSG + (unsigned)a * PS) : own + (unsigned)b * PS;
+#pragma unroll
+        for (int kk = 0; kk < NS; ++kk) g[kk][a] = bload<T>(rg, vo, (unsigned)(kk * 5) * PS);
+      }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < NSA; ++kk)
+#pragma unroll
+        for (int a = 0; a < 5; ++a) g[kk][a] = T(0);
+    }
+  };
+
+  // moments (Eq. 9, 23); terms with a zero velocity component are skipped:
+  // adding +-0 to the running sum would not change it
+  auto moments = [&](const T(&f)[2][9], const T(&g)[NSA][5], Mom<T, NS>& m) {
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
+      m.rho[s] = T(0);
+      m.jx[s] = T(0);
+      m.jy[s] = T(0);
 #pragma unroll
       for (int a = 0; a < 9; ++a) {
-        rho[s] += f[s][a];
-        jx[s] += f[s][a] * T(ex(a));
-        jy[s] += f[s][a] * T(ey(a));
+        m.rho[s] += f[s][a];
+        if (ex(a) != 0) m.jx[s] += f[s][a] * T(ex(a));
+        if (ey(a) != 0) m.jy[s] += f[s][a] * T(ey(a));
       }
     }
-  }
 #pragma unroll
-  for (int k = 0; k < NS; ++k) {
-    T cs = T(0);
+    for (int kk = 0; kk < NSA; ++kk) {
+      T cs = T(0);
 #pragma unroll
-    for (int a = 0; a < 5; ++a) {
-      g[k][a] = liqp ? gi[(k * 5 + a) * plane + idx] : T(0);
-      cs += g[k][a];
+      for (int a = 0; a < 5; ++a) cs += g[kk][a];
+      m.C[kk] = cs;
     }
-    Ck[k] = liqp ? cs : T(0);
-  }
-  T ps = T(0), q1 = T(0), q2 = T(0);
-  unsigned errf = 0;
-  if (validf) {
-    if (!(rho[0] >= T(0)) || !(rho[1] >= T(0)) || (fluid && !(rho[0] + rho[1] > T(0)))) errf |= ERR_DENSITY;
-  }
-  bool clamped = false;
-  if (fluid) {
-    if (c.has_psi) {
-      if (!(T(0.25) * T(c.b) * rho[0] < T(1))) errf |= ERR_EOS;
-      T arg = T(c.psi_pre) * (p_cs<T>(c, rho[0]) - rho[0] / T(3)) / T(c.G11);
-      if (arg < T(0)) {
-        arg = T(0);
-        clamped = true;
-      }
-      ps = dsqrt<T>(arg);
-    }
-    if (c.has_phi1) q1 = T(1) - dexp<T>(-rho[1] / T(c.rho20));
-    if (c.has_phi2) q2 = T(c.a0) - dexp<T>(-rho[0] / T(c.rho10));
-  }
-  s_r1[ty][tx] = rho[0];
-  s_r2[ty][tx] = rho[1];
-  s_ps[ty][tx] = ps;
-  s_q1[ty][tx] = q1;
-  s_q2[ty][tx] = q2;
-#pragma unroll
-  for (int k = 0; k < NS; ++k) s_C[k][ty][tx] = Ck[k];
-  if (own && errf && !EXPORT) {
-    atomicOr(&A.err[0], errf);
-    atomicMin(&A.err[1], (unsigned)(Yw * nx + Xw));
-  }
-  __syncthreads();
-
-  // ------------------------------------------------------------ phase 2
-  auto TT = [&](int dx, int dy) -> uint8_t { return s_t[ty + 1 + dy][tx + 1 + dx]; };
-  auto nb_idx = [&](int a) -> long long {
-    int Xn = Xw + ex(a), Yn = Yw + ey(a);
-    if (Xn < 0) Xn += nx; else if (Xn >= nx) Xn -= nx;
-    if (Yn < 0) Yn += ny; else if (Yn >= ny) Yn -= ny;
-    return (long long)Yn * pitch + Xn;
   };
-  auto is_fluid = [](uint8_t v) { return (v & (TB_WALL | TB_T)) == 0; };
-  auto is_rsolid = [](uint8_t v) { return !(v & TB_WALL) && (v & TB_T) >= T_D; };
 
-  // per-thread balance contributions (common ones in registers, rare ones via LDS)
+  // effective masses: psi_1 from the CS EOS (Eq. 12, 13), phi_1, phi_2 (Eq. 15)
+  auto effmass = [&](bool fluid, const T(&rho)[2], T& ps, T& q1, T& q2, bool& clamped, unsigned& errf) {
+    ps = q1 = q2 = T(0);
+    clamped = false;
+    if (fluid) {
+      if (c.has_psi) {
+        if (!(T(0.25) * k.b * rho[0] < T(1))) errf |= ERR_EOS;
+        T arg = cdiv<T>(k.psi_pre * (p_cs<T>(k, rho[0]) - cdiv<T>(rho[0], T(3), T(1.0 / 3.0))), k.G11, k.r_G11);
+        if (arg < T(0)) {
+          arg = T(0);
+          clamped = true;
+        }
+        ps = dsqrt<T>(arg);
+      }
+      if (c.has_phi1) q1 = T(1) - dexp<T>(-cdiv<T>(rho[1], k.rho20, k.r_rho20));
+      if (c.has_phi2) q2 = k.a0 - dexp<T>(-cdiv<T>(rho[0], k.rho10, k.r_rho10));
+    }
+  };
+
+  auto col_offsets = [&](int Xw, unsigned (&co)[3]) {
+    int xm = Xw - 1, xp = Xw + 1;
+    if (xm < 0) xm += nx;
+    if (xp >= nx) xp -= nx;
+    co[0] = (unsigned)xm * ES;
+    co[1] = (unsigned)Xw * ES;
+    co[2] = (unsigned)xp * ES;
+  };
+
+  // ------------------------------------------------------------ halo columns
+  {
+    const int hs = lane >> 5, hr = lane & 31;
+    const bool hact = hr < nrow + 2;
+    int HX = hs ? x0 + SW : x0 - 1, HY = y0 - 1 + hr;
+    const bool indom = hact && wrap(HX, nx, c.per_x) && wrap(HY, ny, c.per_y);
+    const uint32_t hw = indom ? bload<uint32_t>(rt, (unsigned)HX * 4u, (unsigned)HY * upitch * 4u) : (uint32_t)TB_WALL;
+    const int t = (int)(hw & TB_T);
+    const bool fluid = indom && t == T_FLUID;
+    const bool validf = indom && (t == T_FLUID || (hw & TB_STR));
+    const bool liqp = indom && (hw & TB_LIQP);
+    unsigned co[3];
+    col_offsets(indom ? HX : 0, co);
+    T f[2][9], g[NSA][5];
+    pull(co, indom ? HY : 0, hw, validf, liqp, f, g);
+    Mom<T, NS> m;
+    moments(f, g, m);
+    T ps, q1, q2;
+    bool cl;
+    unsigned ef = 0;
+    effmass(fluid, m.rho, ps, q1, q2, cl, ef);
+    if (hact) {
+      L.hpq[hs][hr] = PQ<T>{ps, q1, q2, flags_as<T>(indom ? flags_w(hw) : (uint32_t)TB_WALL)};
+      L.hr1[hs][hr] = m.rho[0];
+      L.hr2[hs][hr] = m.rho[1];
+#pragma unroll
+      for (int kk = 0; kk < NSA; ++kk) L.hC[kk][hs][hr] = m.C[kk];
+    }
+  }
+
+  // this lane's column
+  int Xw = x0 + lane;
+  const bool colin = wrap(Xw, nx, c.per_x);
+  const int X = x0 + lane;
+  const bool colown = X < nx;
+  unsigned co[3];
+  col_offsets(colin ? Xw : 0, co);
+
+  // per-lane balance contributions over the item's rows
   T l_msrc[2] = {T(0), T(0)};
   T l_ssrc[NSA], l_shet[NSA];
 #pragma unroll
-  for (int k = 0; k < NSA; ++k) l_ssrc[k] = l_shet[k] = T(0);
+  for (int kk = 0; kk < NSA; ++kk) l_ssrc[kk] = l_shet[kk] = T(0);
   double l_vdv = 0.0;
-  double my_rmax = 0.0;
-  bool precip = false;
-  const double thr = c.lfrac * __longlong_as_double((long long)A.rmax[A.slot_prev]);
+  T my_rmax = T(0);
+  double rprev = 0.0;
+#pragma unroll
+  for (int xc = 0; xc < 8; ++xc)
+    rprev = fmax(rprev, __longlong_as_double((long long)A.rmax[A.slot_prev * RM_SLOT + xc * RM_STRIDE]));
+  const double thr = c.lfrac * rprev;
 
-  if (own && fluid) {
-    my_rmax = (double)rho[0];
-    // forces: Eq. 11 (cohesion), 14 (inter-component), 16 (adhesion), body force.
-    // Non-fluid neighbours carry the centre's own psi / phi and s = 1.
-    T c1x = 0, c1y = 0, c12x = 0, c12y = 0, c21x = 0, c21y = 0, swx = 0, swy = 0;
-#pragma unroll
-    for (int a = 1; a < 9; ++a) {
-      const uint8_t nt = TT(ex(a), ey(a));
-      const bool fl = is_fluid(nt);
-      const int ly = ty + ey(a), lx = tx + ex(a);
-      const T psn = fl ? s_ps[ly][lx] : ps;
-      const T q2n = fl ? s_q2[ly][lx] : q2;
-      const T q1n = fl ? s_q1[ly][lx] : q1;
-      const T sw = fl ? T(0) : T(1);
-      c1x += T(wf(a)) * psn * T(ex(a));
-      c1y += T(wf(a)) * psn * T(ey(a));
-      c12x += T(wf(a)) * q2n * T(ex(a));
-      c12y += T(wf(a)) * q2n * T(ey(a));
-      c21x += T(wf(a)) * q1n * T(ex(a));
-      c21y += T(wf(a)) * q1n * T(ey(a));
-      swx += T(wf(a)) * sw * T(ex(a));
-      swy += T(wf(a)) * sw * T(ey(a));
-    }
-    const T r1 = rho[0], r2 = rho[1];
-    T Fx[2], Fy[2];
-    Fx[0] = -T(c.G11) * ps * c1x - T(c.G12) * q1 * c12x - T(c.w1) * ps * swx + r1 * T(c.gx);
-    Fy[0] = -T(c.G11) * ps * c1y - T(c.G12) * q1 * c12y - T(c.w1) * ps * swy + r1 * T(c.gy);
-    Fx[1] = -T(c.G21) * q2 * c21x - T(c.w2) * r2 * swx + r2 * T(c.gx);
-    Fy[1] = -T(c.G21) * q2 * c21y - T(c.w2) * r2 * swy + r2 * T(c.gy);
-    // velocities: Eq. 18 (common), 17 (shifted equilibrium), 19 (physical)
-    const T t1 = T(c.tau[0]), t2 = T(c.tau[1]);
-    const T den = r1 / t1 + r2 / t2;
-    const T upx = (jx[0] / t1 + jx[1] / t2) / den;
-    const T upy = (jy[0] / t1 + jy[1] / t2) / den;
-    T ux[2], uy[2];
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const T r = rho[s], ts = T(c.tau[s]);
-      ux[s] = upx;
-      uy[s] = upy;
-      if (r > T(1e-12)) {
-        ux[s] = upx + ts * Fx[s] / r;
-        uy[s] = upy + ts * Fy[s] / r;
-      }
-    }
-    const T rt = r1 + r2;
-    const T urx = (jx[0] + jx[1] + T(0.5) * (Fx[0] + Fx[1])) / rt;
-    const T ury = (jy[0] + jy[1] + T(0.5) * (Fy[0] + Fy[1])) / rt;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 
-    if (EXPORT) {
-      A.o_ux[idx] = (double)urx;
-      A.o_uy[idx] = (double)ury;
-    } else {
-      // homogeneous reactions at liquid nodes (Eq. 5a, 5c, 27, 28)
-      T Sk[NSA];
-#pragma unroll
-      for (int k = 0; k < NSA; ++k) Sk[k] = T(0);
-      T Ss[2] = {T(0), T(0)};
-      if (liq) {
-        for (int r = 0; r < c.nhom; ++r) {
-          const int re0 = c.hre0[r], re1 = c.hre1[r], pr0 = c.hpr0[r], pr1 = c.hpr1[r];
-          T R;
-          if (c.hkind[r] == HOM_FIRST) {
-            R = T(c.hk[r]) * sel<NS>(Ck, re0);
-          } else if (c.hkind[r] == HOM_BI) {
-            R = T(c.hk[r]) * sel<NS>(Ck, re0) * sel<NS>(Ck, re1);
-          } else {
-            T cg = r2 / T(c.hMgas[r]);
-            if (cg < T(0)) cg = T(0);
-            R = T(c.hk[r]) * (sel<NS>(Ck, re0) - sel<NS>(Ck, pr0) * dsqrt<T>(cg) / T(c.hKeq[r]));
-            Ss[0] -= T(0.5) * R * T(c.hMgas[r]);
-            Ss[1] += T(0.5) * R * T(c.hMgas[r]);
-          }
-          addto<NS>(Sk, re0, -R);
-          if (re1 >= 0) addto<NS>(Sk, re1, -R);
-          if (pr0 >= 0) addto<NS>(Sk, pr0, R);
-          if (pr1 >= 0) addto<NS>(Sk, pr1, R);
+  // The march: iteration R pulls row R + 1 into the ring and collides row R.
+  // The first two iterations (R = y0 - 2, y0 - 1) only fill the ring.
+  T fc[2][9], gc[NSA][5];
+  Mom<T, NS> mc;
+  uint32_t w_cur = 0, w_next = word_at(X, y0 - 1);
+  int sm = 1, s0 = 2, sp = 0;
+  for (int R = y0 - 2; R < y1; ++R) {
+    const int Rn = R + 1;
+    const uint32_t w_nn = word_at(X, R + 2);  // next iteration's row, loaded ahead
+    T fn[2][9], gn[NSA][5];
+    Mom<T, NS> mn;
+    {
+      // ---------------------------------------------------- phase 1, row R + 1
+      int Yw = Rn;
+      const bool rowin = wrap(Yw, ny, c.per_y);
+      const bool indom = colin && rowin;
+      const uint32_t w = w_next;
+      const int t = (int)(w & TB_T);
+      const bool fluid = indom && t == T_FLUID;
+      const bool validf = indom && (t == T_FLUID || (w & TB_STR));
+      const bool liqp = indom && (w & TB_LIQP);
+      pull(co, rowin ? Yw : 0, w, validf, liqp, fn, gn);
+      moments(fn, gn, mn);
+      unsigned errf = 0;
+      if (validf && (!(mn.rho[0] >= T(0)) || !(mn.rho[1] >= T(0)) || (fluid && !(mn.rho[0] + mn.rho[1] > T(0)))))
+        errf |= ERR_DENSITY;
+      T ps, q1, q2;
+      bool clamped;
+      effmass(fluid, mn.rho, ps, q1, q2, clamped, errf);
+      if (!EXPORT && colown && Rn >= y0 && Rn < y1) {
+        if (errf) {
+          atomicOr(&A.err[0], errf);
+          atomicMin(&A.err[1], (unsigned)(Rn * nx + X));
         }
-        l_msrc[0] = Ss[0];
-        l_msrc[1] = Ss[1];
-#pragma unroll
-        for (int k = 0; k < NS; ++k) l_ssrc[k] = Sk[k];
+        if (clamped) atomicAdd(&L.rare[5], 1.0);
       }
-      // flow collision (Eq. 6, 8)
+      const int cl = lane + 1;
+      L.pq[sp][cl] = PQ<T>{ps, q1, q2, flags_as<T>(indom ? flags_w(w) : (uint32_t)TB_WALL)};
+      L.r1[sp][cl] = mn.rho[0];
+      L.r2[sp][cl] = mn.rho[1];
 #pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        const T om = T(c.om[s]);
-        const T usq = ux[s] * ux[s] + uy[s] * uy[s];
+      for (int kk = 0; kk < NSA; ++kk) L.C[kk][sp][cl] = mn.C[kk];
+      if (lane < 2) {
+        const int ce = lane ? SW + 1 : 0;
+        const int hr = Rn - (y0 - 1);
+        L.pq[sp][ce] = L.hpq[lane][hr];
+        L.r1[sp][ce] = L.hr1[lane][hr];
+        L.r2[sp][ce] = L.hr2[lane][hr];
 #pragma unroll
-        for (int a = 0; a < 9; ++a) {
-          const T eu = T(ex(a)) * ux[s] + T(ey(a)) * uy[s];
-          const T feq = T(w9(a)) * rho[s] * (T(1) + T(3) * eu + T(4.5) * eu * eu - T(1.5) * usq);
-          f[s][a] = f[s][a] - om * (f[s][a] - feq) + T(w9(a)) * Ss[s];
-        }
+        for (int kk = 0; kk < NSA; ++kk) L.C[kk][sp][ce] = L.hC[kk][lane][hr];
       }
-      // (a) populations stranded in a node that became SOLID_F last step go,
-      // at rest, equally to that node's fluid D2Q9 neighbours
-      T don[2] = {T(0), T(0)};
-#pragma unroll
-      for (int a = 1; a < 9; ++a) {
-        const uint8_t nt = TT(ex(a), ey(a));
-        if (!(nt & TB_WALL) && (nt & TB_STR)) {
-          int m = 0;
-#pragma unroll
-          for (int b = 1; b < 9; ++b) m += is_fluid(TT(ex(a) + ex(b), ey(a) + ey(b))) ? 1 : 0;
-          don[0] += s_r1[ty + ey(a)][tx + ex(a)] / T(m);
-          don[1] += s_r2[ty + ey(a)][tx + ex(a)] / T(m);
-        }
-      }
-#pragma unroll
-      for (int s = 0; s < 2; ++s)
-        if (don[s] != T(0)) {
-#pragma unroll
-          for (int a = 0; a < 9; ++a) f[s][a] += T(w9(a)) * don[s];
-        }
-      // flow push-streaming with halfway bounce-back
-      T* fo = static_cast<T*>(A.f_out);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+
+    if (R >= y0) {
+      // ---------------------------------------------------- phase 2, row R
+      const uint32_t w = w_cur;
+      const int t = (int)(w & TB_T);
+      const bool own = colown;  // R < y1 <= ny
+      const bool fluid = colin && t == T_FLUID;
+      const bool liq = colin && (w & TB_LIQ);
+      const bool liqp = colin && (w & TB_LIQP);
+      const unsigned idx = (unsigned)R * upitch + (unsigned)X;
+      auto slot = [&](int dy) { return dy < 0 ? sm : (dy > 0 ? sp : s0); };
+      // the flags of the eight neighbours (and their psi, phi)
+      PQ<T> nq[9];
+      uint32_t nt[9];
 #pragma unroll
       for (int a = 0; a < 9; ++a) {
-        const bool tf = a == 0 ? true : is_fluid(TT(ex(a), ey(a)));
-        const long long dst = tf ? (a * plane + (a == 0 ? idx : nb_idx(a))) : (opp(a) * plane + idx);
-        fo[dst] = f[0][a];
-        fo[9 * plane + dst] = f[1][a];
+        nq[a] = L.pq[slot(ey(a))][lane + 1 + ex(a)];
+        nt[a] = flags_of<T>(nq[a].fl);
       }
+      // node flags two links away (rare amendment paths)
+      auto far_flags = [&](int dx, int dy) -> uint32_t {
+        const uint32_t v = word_at(X + dx, R + dy);
+        return (v & TB_WALL) ? (uint32_t)TB_WALL : flags_w(v);
+      };
+      Mom<T, NS>& m = mc;
+      const T ps = nq[0].ps, q1 = nq[0].q1, q2 = nq[0].q2;
+      T(&f)[2][9] = fc;
+      T(&g)[NSA][5] = gc;
 
-      if (NS > 0 && liq) {
-        // solute collision (Eq. 20-22) with the physical velocity u_r
-#pragma unroll
-        for (int k = 0; k < NS; ++k) {
-          const T om = T(c.omg[k]);
-#pragma unroll
-          for (int a = 0; a < 5; ++a) {
-            const T J = T(c.J[k][a]);
-            const T geq = Ck[k] * (J + T(0.5) * (T(ex(a)) * urx + T(ey(a)) * ury));
-            g[k][a] = g[k][a] - om * (g[k][a] - geq) + J * Sk[k];
-          }
-        }
-        // (b) solute of a node that left the liquid set goes, at rest, equally
-        // to its liquid D2Q5 neighbours
-        T donk[NSA];
-#pragma unroll
-        for (int k = 0; k < NSA; ++k) donk[k] = T(0);
-        bool any = false;
-#pragma unroll
-        for (int a = 1; a < 5; ++a) {
-          const uint8_t nt = TT(ex(a), ey(a));
-          if (!(nt & TB_WALL) && (nt & TB_LIQP) && !(nt & TB_LIQ)) {
-            int m = 0;
-#pragma unroll
-            for (int b = 1; b < 5; ++b) {
-              const uint8_t q = TT(ex(a) + ex(b), ey(a) + ey(b));
-              m += (!(q & TB_WALL) && (q & TB_LIQ)) ? 1 : 0;
-            }
-#pragma unroll
-            for (int k = 0; k < NS; ++k) donk[k] += s_C[k][ty + ey(a)][tx + ex(a)] / T(m);
-            any = true;
-          }
-        }
-        if (any) {
-#pragma unroll
-          for (int k = 0; k < NS; ++k)
-#pragma unroll
-            for (int a = 0; a < 5; ++a) g[k][a] += T(c.J[k][a]) * donk[k];
-        }
-        // heterogeneous link fluxes (Eq. 29-31, A2) and the precipitate the
-        // node collects from GROWS reactions (Eq. 35)
-        T phi[LBRX_MAX_RXN];
-        for (int r = 0; r < c.nhet; ++r) {
-          T v = T(c.xkap[r]) * (sel<NS>(Ck, c.xre[r]) - T(c.xCeq[r]));
-          if (c.xirrev[r] && v < T(0)) v = T(0);
-          phi[r] = v;
-        }
-        T* go = static_cast<T*>(A.g_out);
-        double dv = 0.0;
-        bool touched = false;
-#pragma unroll
-        for (int a = 0; a < 5; ++a) {
-          const uint8_t nt = a == 0 ? tb : TT(ex(a), ey(a));
-          const bool tl = a == 0 ? true : (!(nt & TB_WALL) && (nt & TB_LIQ));
-          if (tl) {
-            const long long dst = a * plane + (a == 0 ? idx : nb_idx(a));
-#pragma unroll
-            for (int k = 0; k < NS; ++k) go[k * 5 * plane + dst] = g[k][a];
-          } else {
-            const bool rs = is_rsolid(nt);
-            const int tj = nt & TB_T;
-#pragma unroll
-            for (int k = 0; k < NS; ++k) {
-              T v = g[k][a];
-              if (rs) {
-                for (int r = 0; r < c.nhet; ++r) {
-                  if (!(c.xsurf[r] & (1 << tj))) continue;
-                  if (c.xre[r] == k) {
-                    v -= phi[r];
-                    l_shet[k] -= phi[r];
-                  }
-                  if (c.xpr[r] == k) {
-                    v += phi[r];
-                    l_shet[k] += phi[r];
-                  }
-                }
-              }
-              go[k * 5 * plane + opp(a) * plane + idx] = v;
-            }
-            if (rs && a > 0) {
-              for (int r = 0; r < c.nhet; ++r)
-                if ((c.xsurf[r] & (1 << tj)) && c.xmode[r] == HET_GROWS) {
-                  dv += c.xmvol[r] * (double)phi[r];
-                  touched = true;
-                }
-            }
-          }
-        }
-        if (touched) {
-          const double Vn = A.V[idx] + dv;
-          A.V[idx] = Vn;
-          l_vdv += dv;
-          precip = Vn >= 1.0;  // the precipitate fills the node: SOLID_F next step
-        }
-      }
-    }
-  }
+      bool precip = false;
+      bool storef = false, storeg = false;  // this lane holds valid post-collision populations
 
-  // ---------------------------------------------------------- node status
-  if (!EXPORT && own) {
-    uint8_t tnew = (uint8_t)t;
-    bool lnew = false;
-    if (t == T_FLUID) {
-      if (precip) tnew = T_F;
-      else lnew = (double)rho[0] > thr;
-    } else if (t == T_D || t == T_F) {
-      // volume of pixel at a reactive solid node (Eq. 33; A2): sum of the
-      // fluxes on its D2Q5 links to liquid nodes, in direction then reaction order
-      double dv = 0.0;
-      bool touched = false;
-      if (NS > 0) {
-#pragma unroll
-        for (int a = 1; a < 5; ++a) {
-          const uint8_t nt = TT(ex(a), ey(a));
-          if ((nt & TB_WALL) || !(nt & TB_LIQ)) continue;
-          for (int r = 0; r < c.nhet; ++r) {
-            if (!(c.xsurf[r] & (1 << t))) continue;
-            const int md = c.xmode[r];
-            if (md != HET_CONSUMES && md != HET_MINERAL) continue;
-            T cn = T(0);
-#pragma unroll
-            for (int k = 0; k < NS; ++k)
-              if (k == c.xre[r]) cn = s_C[k][ty + ey(a)][tx + ex(a)];
-            T v = T(c.xkap[r]) * (cn - T(c.xCeq[r]));
-            if (c.xirrev[r] && v < T(0)) v = T(0);
-            if (md == HET_CONSUMES) dv -= c.xmvol[r] * (double)v;
-            else dv += c.xmvol[r] * (double)v;
-            touched = true;
-          }
-        }
-      }
-      double Vn = A.V[idx];
-      if (touched) {
-        Vn += dv;
-        A.V[idx] = Vn;
-        l_vdv += dv;
-      }
-      if (Vn <= 0.0) {
-        int nf = 0;
-        T sum0 = T(0), sum1 = T(0);
+      if (own && fluid) {
+        my_rmax = m.rho[0] > my_rmax ? m.rho[0] : my_rmax;
+        // forces: Eq. 11 (cohesion), 14 (inter-component), 16 (adhesion), body
+        // force.  A non-fluid neighbour counts with the centre's own psi / phi
+        // and s = 1; the ring holds zero psi / phi there, so its share is the
+        // centre's value times the solid-neighbour sum.
+        T c1x = 0, c1y = 0, c12x = 0, c12y = 0, c21x = 0, c21y = 0, swx = 0, swy = 0;
 #pragma unroll
         for (int a = 1; a < 9; ++a) {
-          const uint8_t nt = TT(ex(a), ey(a));
-          if (!is_fluid(nt)) continue;
-          sum0 += s_r1[ty + ey(a)][tx + ex(a)];
-          sum1 += s_r2[ty + ey(a)][tx + ex(a)];
-          ++nf;
-        }
-        if (nf > 0) {
-          // (c) dissolved: fluid from the next step, at rest with the mean
-          // density of its fluid neighbours; no solute yet
-          const T rb0 = sum0 / T(nf), rb1 = sum1 / T(nf);
-          T* fo = static_cast<T*>(A.f_out);
-#pragma unroll
-          for (int a = 0; a < 9; ++a) {
-            fo[a * plane + idx] = T(w9(a)) * rb0;
-            fo[(9 + a) * plane + idx] = T(w9(a)) * rb1;
+          const T sw = is_fluid(nt[a]) ? T(0) : T(1);
+          if (ex(a) != 0) {
+            c1x += T(wf(a) * ex(a)) * nq[a].ps;
+            c12x += T(wf(a) * ex(a)) * nq[a].q2;
+            c21x += T(wf(a) * ex(a)) * nq[a].q1;
+            swx += T(wf(a) * ex(a)) * sw;
           }
-          atomicAdd(&s_rare[0], (double)rb0);
-          atomicAdd(&s_rare[1], (double)rb1);
-          atomicAdd(&s_rare[4], Vn);
-          atomicAdd(&s_rare[6], 1.0);
-          A.V[idx] = 0.0;
-          tnew = T_FLUID;
-          lnew = (double)rb0 > thr;
+          if (ey(a) != 0) {
+            c1y += T(wf(a) * ey(a)) * nq[a].ps;
+            c12y += T(wf(a) * ey(a)) * nq[a].q2;
+            c21y += T(wf(a) * ey(a)) * nq[a].q1;
+            swy += T(wf(a) * ey(a)) * sw;
+          }
+        }
+        c1x += ps * swx;
+        c1y += ps * swy;
+        c12x += q2 * swx;
+        c12y += q2 * swy;
+        c21x += q1 * swx;
+        c21y += q1 * swy;
+        const T r1 = m.rho[0], r2 = m.rho[1];
+        T Fx[2], Fy[2];
+        Fx[0] = -k.G11 * ps * c1x - k.G12 * q1 * c12x - k.w1 * ps * swx + r1 * k.gx;
+        Fy[0] = -k.G11 * ps * c1y - k.G12 * q1 * c12y - k.w1 * ps * swy + r1 * k.gy;
+        Fx[1] = -k.G21 * q2 * c21x - k.w2 * r2 * swx + r2 * k.gx;
+        Fy[1] = -k.G21 * q2 * c21y - k.w2 * r2 * swy + r2 * k.gy;
+        // velocities: Eq. 18 (common), 17 (shifted equilibrium), 19 (physical)
+        const T den = cdiv<T>(r1, k.tau[0], k.r_tau[0]) + cdiv<T>(r2, k.tau[1], k.r_tau[1]);
+        const T upx = qdiv<T>(cdiv<T>(m.jx[0], k.tau[0], k.r_tau[0]) + cdiv<T>(m.jx[1], k.tau[1], k.r_tau[1]), den);
+        const T upy = qdiv<T>(cdiv<T>(m.jy[0], k.tau[0], k.r_tau[0]) + cdiv<T>(m.jy[1], k.tau[1], k.r_tau[1]), den);
+        T ux[2], uy[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          const T r = m.rho[s];
+          ux[s] = upx;
+          uy[s] = upy;
+          if (r > T(1e-12)) {
+            ux[s] = upx + qdiv<T>(k.tau[s] * Fx[s], r);
+            uy[s] = upy + qdiv<T>(k.tau[s] * Fy[s], r);
+          }
+        }
+        const T rt_ = r1 + r2;
+        const T urx = qdiv<T>(m.jx[0] + m.jx[1] + T(0.5) * (Fx[0] + Fx[1]), rt_);
+        const T ury = qdiv<T>(m.jy[0] + m.jy[1] + T(0.5) * (Fy[0] + Fy[1]), rt_);
+
+        if (EXPORT) {
+          A.o_ux[idx] = (double)urx;
+          A.o_uy[idx] = (double)ury;
+        } else {
+          // homogeneous reactions at liquid nodes (Eq. 5a, 5c, 27, 28); the
+          // species sources are the net stoichiometric coefficients times the rates
+          T Sk[NSA];
+#pragma unroll
+          for (int kk = 0; kk < NSA; ++kk) Sk[kk] = T(0);
+          T Ss[2] = {T(0), T(0)};
+          if (liq) {
+            for (int r = 0; r < c.nhom; ++r) {
+              T Rr;
+              if (c.hkind[r] == HOM_FIRST) {
+                Rr = k.hk[r] * sel<NS>(m.C, c.hre0[r]);
+              } else if (c.hkind[r] == HOM_BI) {
+                Rr = k.hk[r] * sel<NS>(m.C, c.hre0[r]) * sel<NS>(m.C, c.hre1[r]);
+              } else {
+                T cg = cdiv<T>(r2, k.hMgas[r], k.r_hMgas[r]);
+                if (cg < T(0)) cg = T(0);
+                Rr = k.hk[r] * (sel<NS>(m.C, c.hre0[r]) -
+                                cdiv<T>(sel<NS>(m.C, c.hpr0[r]) * dsqrt<T>(cg), k.hKeq[r], k.r_hKeq[r]));
+                Ss[0] -= T(0.5) * Rr * k.hMgas[r];
+                Ss[1] += T(0.5) * Rr * k.hMgas[r];
+              }
+#pragma unroll
+              for (int kk = 0; kk < NS; ++kk) Sk[kk] += k.hnu[r][kk] * Rr;
+            }
+            l_msrc[0] += Ss[0];
+            l_msrc[1] += Ss[1];
+#pragma unroll
+            for (int kk = 0; kk < NS; ++kk) l_ssrc[kk] += Sk[kk];
+          }
+          // flow collision (Eq. 6, 8)
+#pragma unroll
+          for (int s = 0; s < 2; ++s) {
+            const T om = k.om[s];
+            const T usq = ux[s] * ux[s] + uy[s] * uy[s];
+            if constexpr (std::is_same<T, double>::value) {
+              // literal Eq. 6 and 8
+#pragma unroll
+              for (int a = 0; a < 9; ++a) {
+                const T eu = (ex(a) == 0 ? T(0) : T(ex(a)) * ux[s]) + (ey(a) == 0 ? T(0) : T(ey(a)) * uy[s]);
+                const T feq = T(w9(a)) * m.rho[s] * (T(1) + T(3) * eu + T(4.5) * eu * eu - T(1.5) * usq);
+                f[s][a] = f[s][a] - om * (f[s][a] - feq) + T(w9(a)) * Ss[s];
+              }
+            } else {
+              // the same update factored: f* = (1-om) f + om w rho (1 - 1.5 u^2 + eu (3 + 4.5 eu)) + w S
+              const T oneom = T(1) - om;
+              const T base = T(1) - T(1.5) * usq;
+#pragma unroll
+              for (int a = 0; a < 9; ++a) {
+                const T eu = (ex(a) == 0 ? T(0) : T(ex(a)) * ux[s]) + (ey(a) == 0 ? T(0) : T(ey(a)) * uy[s]);
+                const T wr = T(w9(a)) * om * m.rho[s];
+                f[s][a] = oneom * f[s][a] + wr * (base + eu * (T(3) + T(4.5) * eu)) + T(w9(a)) * Ss[s];
+              }
+            }
+          }
+          // (a) populations stranded in a node that became SOLID_F last step go,
+          // at rest, equally to that node's fluid D2Q9 neighbours
+          bool any_str = false;
+#pragma unroll
+          for (int a = 1; a < 9; ++a) any_str |= !(nt[a] & TB_WALL) && (nt[a] & TB_STR);
+          if (any_str) {
+            T don[2] = {T(0), T(0)};
+#pragma unroll
+            for (int a = 1; a < 9; ++a) {
+              if (!(nt[a] & TB_WALL) && (nt[a] & TB_STR)) {
+                int mm = 0;
+                for (int b = 1; b < 9; ++b) mm += is_fluid(far_flags(ex(a) + ex(b), ey(a) + ey(b))) ? 1 : 0;
+                const int sl = slot(ey(a)), lx = lane + 1 + ex(a);
+                don[0] += L.r1[sl][lx] / T(mm);
+                don[1] += L.r2[sl][lx] / T(mm);
+              }
+            }
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+              if (don[s] != T(0)) {
+#pragma unroll
+                for (int a = 0; a < 9; ++a) f[s][a] += T(w9(a)) * don[s];
+              }
+          }
+          storef = true;
+
+          if (NS > 0 && liq) {
+            // solute collision (Eq. 20-22) with the physical velocity u_r
+#pragma unroll
+            for (int kk = 0; kk < NS; ++kk) {
+              const T om = k.omg[kk];
+              if constexpr (std::is_same<T, double>::value) {
+                // literal Eq. 20 and 21
+#pragma unroll
+                for (int a = 0; a < 5; ++a) {
+                  const T J = k.J[kk][a];
+                  const T eu = (ex(a) == 0 ? T(0) : T(ex(a)) * urx) + (ey(a) == 0 ? T(0) : T(ey(a)) * ury);
+                  const T geq = m.C[kk] * (J + T(0.5) * eu);
+                  g[kk][a] = g[kk][a] - om * (g[kk][a] - geq) + J * Sk[kk];
+                }
+              } else {
+                // factored: g* = (1-om) g + J (om C + S) + (om C / 2) e.u
+                const T oneom = T(1) - om;
+                const T omC = om * m.C[kk];
+                const T hx = T(0.5) * omC * urx, hy = T(0.5) * omC * ury;
+                const T b0 = k.J[kk][0] * (omC + Sk[kk]);
+                const T b1 = k.J[kk][1] * (omC + Sk[kk]);
+                g[kk][0] = oneom * g[kk][0] + b0;
+                g[kk][1] = oneom * g[kk][1] + b1 + hx;
+                g[kk][2] = oneom * g[kk][2] + b1 + hy;
+                g[kk][3] = oneom * g[kk][3] + b1 - hx;
+                g[kk][4] = oneom * g[kk][4] + b1 - hy;
+              }
+            }
+            // (b) solute of a node that left the liquid set goes, at rest, equally
+            // to its liquid D2Q5 neighbours
+            bool any_don = false;
+#pragma unroll
+            for (int a = 1; a < 5; ++a) any_don |= !(nt[a] & TB_WALL) && (nt[a] & TB_LIQP) && !(nt[a] & LF_LIQN);
+            if (any_don) {
+              T donk[NSA];
+#pragma unroll
+              for (int kk = 0; kk < NSA; ++kk) donk[kk] = T(0);
+#pragma unroll
+              for (int a = 1; a < 5; ++a) {
+                if (!(nt[a] & TB_WALL) && (nt[a] & TB_LIQP) && !(nt[a] & LF_LIQN)) {
+                  int mm = 0;
+                  for (int b = 1; b < 5; ++b) mm += is_liq(far_flags(ex(a) + ex(b), ey(a) + ey(b))) ? 1 : 0;
+                  const int sl = slot(ey(a)), lx = lane + 1 + ex(a);
+#pragma unroll
+                  for (int kk = 0; kk < NS; ++kk) donk[kk] += L.C[kk][sl][lx] / T(mm);
+                }
+              }
+#pragma unroll
+              for (int kk = 0; kk < NS; ++kk)
+#pragma unroll
+                for (int a = 0; a < 5; ++a) g[kk][a] += k.J[kk][a] * donk[kk];
+            }
+            // heterogeneous link fluxes (Eq. 29-31, A2): a population heading into a
+            // reactive solid comes back next step minus the reactant's (plus the
+            // product's) link flux; the node also collects the precipitate of GROWS
+            // reactions (Eq. 35)
+            bool any_rs = false;
+#pragma unroll
+            for (int a = 1; a < 5; ++a) any_rs |= is_rsolid(nt[a]);
+            if (any_rs) {
+              T phi[LBRX_MAX_RXN];
+              for (int r = 0; r < c.nhet; ++r) {
+                T v = k.xkap[r] * (sel<NS>(m.C, c.xre[r]) - k.xCeq[r]);
+                if (c.xirrev[r] && v < T(0)) v = T(0);
+                phi[r] = v;
+              }
+              double dv = 0.0;
+              bool touched = false;
+#pragma unroll
+              for (int a = 1; a < 5; ++a) {
+                if (!is_rsolid(nt[a])) continue;
+                const int tj = nt[a] & TB_T;
+#pragma unroll
+                for (int kk = 0; kk < NS; ++kk) {
+                  for (int r = 0; r < c.nhet; ++r) {
+                    if (!(c.xsurf[r] & (1 << tj))) continue;
+                    if (c.xre[r] == kk) {
+                      g[kk][a] -= phi[r];
+                      l_shet[kk] -= phi[r];
+                    }
+                    if (c.xpr[r] == kk) {
+                      g[kk][a] += phi[r];
+                      l_shet[kk] += phi[r];
+                    }
+                  }
+                }
+                for (int r = 0; r < c.nhet; ++r)
+                  if ((c.xsurf[r] & (1 << tj)) && c.xmode[r] == HET_GROWS) {
+                    dv += c.xmvol[r] * (double)phi[r];
+                    touched = true;
+                  }
+              }
+              if (touched) {
+                const double Vn = A.V[idx] + dv;
+                A.V[idx] = Vn;
+                l_vdv += dv;
+                precip = Vn >= 1.0;  // the precipitate fills the node: SOLID_F next step
+              }
+            }
+            storeg = true;
+          }
         }
       }
-      if (tb & TB_STR) {
-        int m = 0;
+
+      // ------------------------------------------------------ node status
+      uint32_t wout = 0;
+      if (!EXPORT && own) {
+        bool dissolved = false;
+        uint32_t tnew = (uint32_t)t;
+        bool lnew = false;
+        if (t == T_FLUID) {
+          if (precip) tnew = T_F;
+          else lnew = (double)m.rho[0] > thr;
+        } else if (t == T_D || t == T_F) {
+          // volume of pixel at a reactive solid node (Eq. 33; A2): sum of the
+          // fluxes on its D2Q5 links to liquid nodes, in direction then reaction order
+          double dv = 0.0;
+          bool touched = false;
+          if (NS > 0) {
 #pragma unroll
-        for (int b = 1; b < 9; ++b) m += is_fluid(TT(ex(b), ey(b))) ? 1 : 0;
-        if (m == 0) {
-          atomicAdd(&s_rare[2], (double)rho[0]);
-          atomicAdd(&s_rare[3], (double)rho[1]);
+            for (int a = 1; a < 5; ++a) {
+              if (!is_liq(nt[a])) continue;
+              const int sl = slot(ey(a)), lx = lane + 1 + ex(a);
+              for (int r = 0; r < c.nhet; ++r) {
+                if (!(c.xsurf[r] & (1 << t))) continue;
+                const int md = c.xmode[r];
+                if (md != HET_CONSUMES && md != HET_MINERAL) continue;
+                T cn = T(0);
+#pragma unroll
+                for (int kk = 0; kk < NS; ++kk)
+                  if (kk == c.xre[r]) cn = L.C[kk][sl][lx];
+                T v = k.xkap[r] * (cn - k.xCeq[r]);
+                if (c.xirrev[r] && v < T(0)) v = T(0);
+                if (md == HET_CONSUMES) dv -= c.xmvol[r] * (double)v;
+                else dv += c.xmvol[r] * (double)v;
+                touched = true;
+              }
+            }
+          }
+          double Vn = A.V[idx];
+          if (touched) {
+            Vn += dv;
+            A.V[idx] = Vn;
+            l_vdv += dv;
+          }
+          if (Vn <= 0.0) {
+            int nf = 0;
+            T sum0 = T(0), sum1 = T(0);
+#pragma unroll
+            for (int a = 1; a < 9; ++a) {
+              if (!is_fluid(nt[a])) continue;
+              const int sl = slot(ey(a)), lx = lane + 1 + ex(a);
+              sum0 += L.r1[sl][lx];
+              sum1 += L.r2[sl][lx];
+              ++nf;
+            }
+            if (nf > 0) {
+              // (c) dissolved: fluid from the next step, at rest with the mean
+              // density of its fluid neighbours and no solute.  Its next status
+              // word names no fluid neighbour, so the next pull reads its own
+              // slots back (slot opp(a) for direction a: the rest populations
+              // are the same in opposite directions).
+              const T rb0 = sum0 / T(nf), rb1 = sum1 / T(nf);
+#pragma unroll
+              for (int a = 0; a < 9; ++a) {
+                f[0][a] = T(w9(a)) * rb0;
+                f[1][a] = T(w9(a)) * rb1;
+              }
+              storef = true;
+              dissolved = true;
+              atomicAdd(&L.rare[0], (double)rb0);
+              atomicAdd(&L.rare[1], (double)rb1);
+              atomicAdd(&L.rare[4], Vn);
+              atomicAdd(&L.rare[6], 1.0);
+              A.V[idx] = 0.0;
+              tnew = T_FLUID;
+              lnew = (double)rb0 > thr;
+            }
+          }
+          if (w & TB_STR) {
+            int mm = 0;
+#pragma unroll
+            for (int b = 1; b < 9; ++b) mm += is_fluid(nt[b]) ? 1 : 0;
+            if (mm == 0) {
+              atomicAdd(&L.rare[2], (double)m.rho[0]);
+              atomicAdd(&L.rare[3], (double)m.rho[1]);
+            }
+          }
+        }
+        // a node leaving the liquid set with no liquid neighbour to take its solute
+        if (liqp && !liq) {
+          int mm = 0;
+#pragma unroll
+          for (int b = 1; b < 5; ++b) mm += is_liq(nt[b]) ? 1 : 0;
+          if (mm == 0) {
+#pragma unroll
+            for (int kk = 0; kk < NS; ++kk) atomicAdd(&L.rare[8 + kk], (double)m.C[kk]);
+          }
+          if (t == T_FLUID) atomicAdd(&L.rare[16], 1.0);
+        }
+        if (liq && !liqp) atomicAdd(&L.rare[17], 1.0);
+        const bool to_f = (t == T_FLUID && tnew == T_F);
+        if (to_f) atomicAdd(&L.rare[7], 1.0);
+        // status word of the next step: type, liquid marks, stranded flag, and
+        // which neighbours are fluid / liquid now (the next pull follows them)
+        wout = tnew | (lnew ? TB_LIQ : 0u) | (liq ? TB_LIQP : 0u) | (to_f ? TB_STR : 0u);
+        if (!dissolved) {
+#pragma unroll
+          for (int b = 1; b < 9; ++b) wout |= (nt[b] & LF_FLU) << (NBF_SHIFT + b - 1 - 6);
+#pragma unroll
+          for (int b = 1; b < 5; ++b) wout |= (nt[b] & LF_LIQN) << (NBL_SHIFT + b - 1 - 5);
+        }
+      }
+
+      if (EXPORT) {
+        if (own) {
+          A.o_r1[idx] = (double)m.rho[0];
+          A.o_r2[idx] = (double)m.rho[1];
+          if (!fluid) {
+            A.o_ux[idx] = 0.0;
+            A.o_uy[idx] = 0.0;
+          }
+#pragma unroll
+          for (int kk = 0; kk < NS; ++kk) A.o_C[(size_t)kk * c.plane + idx] = (double)m.C[kk];
+        }
+      } else {
+        // -------------------------------------------------- own-slot stores
+        // Every lane writes its node's slots at the unwrapped column (a lane
+        // past nx writes into the row padding).  A 32-lane group writes all its
+        // lanes when any of them holds valid populations, so that lines are
+        // written whole; a lane without valid populations writes values nobody
+        // reads (its slots are not pulled from next step).
+        const __amdgpu_buffer_rsrc_t wf_ = rsrc_of(A.f_out, c.fbytes);
+        const __amdgpu_buffer_rsrc_t wg_ = rsrc_of(A.g_out, c.gbytes);
+        const __amdgpu_buffer_rsrc_t wt_ = rsrc_of(A.t_out, c.tbytes);
+        bstore<uint32_t>(wout, wt_, (unsigned)X * 4u, (unsigned)R * upitch * 4u);
+        const unsigned long long bf = __ballot(storef);
+        const unsigned long long bg = __ballot(storeg);
+        const int half = lane >> 5;
+        const bool gf = ((bf >> (32 * half)) & 0xffffffffull) != 0ull;
+        const bool gg = ((bg >> (32 * half)) & 0xffffffffull) != 0ull;
+        const unsigned xo = (unsigned)X * ES;
+        if (gf) {
+          const unsigned vo = xo + (unsigned)R * RSF;
+#pragma unroll
+          for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int a = 0; a < 9; ++a) bstore<T>(f[s][a], wf_, vo, (unsigned)(s * 9 + a) * PS);
+        }
+        if (NS > 0 && gg) {
+          const unsigned vo = xo + (unsigned)R * RSG;
+#pragma unroll
+          for (int kk = 0; kk < NS; ++kk)
+#pragma unroll
+            for (int a = 0; a < 5; ++a) bstore<T>(g[kk][a], wg_, vo, (unsigned)(kk * 5 + a) * PS);
         }
       }
     }
-    if (clamped) atomicAdd(&s_rare[5], 1.0);
-    // a node leaving the liquid set with no liquid neighbour to take its solute
-    if (liqp && !liq) {
-      int m = 0;
-#pragma unroll
-      for (int b = 1; b < 5; ++b) {
-        const uint8_t q = TT(ex(b), ey(b));
-        m += (!(q & TB_WALL) && (q & TB_LIQ)) ? 1 : 0;
-      }
-      if (m == 0) {
-#pragma unroll
-        for (int k = 0; k < NS; ++k) atomicAdd(&s_rare[8 + k], (double)Ck[k]);
-      }
-      if (t == T_FLUID) atomicAdd(&s_rare[16], 1.0);
-    }
-    if (liq && !liqp) atomicAdd(&s_rare[17], 1.0);
-    const bool to_f = (t == T_FLUID && tnew == T_F);
-    if (to_f) atomicAdd(&s_rare[7], 1.0);
-    uint8_t nbyte = (uint8_t)(tnew | (lnew ? TB_LIQ : 0) | (liq ? TB_LIQP : 0) | (to_f ? TB_STR : 0));
-    A.t_out[idx] = nbyte;
-  }
 
-  if (EXPORT) {
-    if (own) {
-      A.o_r1[idx] = (double)rho[0];
-      A.o_r2[idx] = (double)rho[1];
-      if (!fluid) {
-        A.o_ux[idx] = 0.0;
-        A.o_uy[idx] = 0.0;
-      }
+    // next row
 #pragma unroll
-      for (int k = 0; k < NS; ++k) A.o_C[k * plane + idx] = (double)Ck[k];
-    }
-    return;
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int a = 0; a < 9; ++a) fc[s][a] = fn[s][a];
+#pragma unroll
+    for (int kk = 0; kk < NSA; ++kk)
+#pragma unroll
+      for (int a = 0; a < 5; ++a) gc[kk][a] = gn[kk][a];
+    mc = mn;
+    w_cur = w_next;
+    w_next = w_nn;
+    const int s_old = sm;
+    sm = s0;
+    s0 = sp;
+    sp = s_old;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   }
+  if (EXPORT) return;
 
-  // ---------------------------------------------------------- reductions
-  // step maximum of rho_1 over fluid nodes
-  {
-    const double wm = wave_max(my_rmax);
-    if (tx == 0) s_rmax[ty] = wm;
-  }
-  // common balances: per-wave sums in registers, then per tile in fixed order
-  {
-    double v;
-    v = wave_sum((double)l_msrc[0]);
-    if (tx == 0) s_red[ty][0] = v;
-    v = wave_sum((double)l_msrc[1]);
-    if (tx == 0) s_red[ty][1] = v;
-    v = wave_sum(l_vdv);
-    if (tx == 0) s_red[ty][2] = v;
+  // ---------------------------------------------------------- item balances
+  // Wave sums in the working precision (a wave whose values are all zero skips
+  // the shuffles), added to this item's FP64 record (the item is this
+  // wavefront's alone, so plain read-modify-write).
+  const T wm = wave_max_t(my_rmax);
+  const T v0 = wave_sum_t(l_msrc[0]);
+  const T v1 = wave_sum_t(l_msrc[1]);
+  const double vd = wave_sum_t(l_vdv);
+  T vs[NSA], vh[NSA];
 #pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      v = wave_sum((double)l_ssrc[k]);
-      if (tx == 0) s_red[ty][4 + k] = v;
-      v = wave_sum((double)l_shet[k]);
-      if (tx == 0) s_red[ty][4 + NSA + k] = v;
+  for (int kk = 0; kk < NSA; ++kk) {
+    vs[kk] = wave_sum_t(l_ssrc[kk]);
+    vh[kk] = wave_sum_t(l_shet[kk]);
+  }
+  double* Lg = A.led + (size_t)item * NLED;
+  if (lane == 0) {
+    const double md = (double)wm;
+    unsigned long long* part = &A.rmax[A.slot_cur * RM_SLOT + xcd * RM_STRIDE];
+    const unsigned long long mb = (unsigned long long)__double_as_longlong(md);
+    // the partial only grows during a step, so a value already at least as
+    // large makes this wavefront's atomic unnecessary
+    const unsigned long long seen = __hip_atomic_load(part, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (md > 0.0 && mb > seen) atomicMax(part, mb);
+    if (item == 0)
+      for (int xc = 0; xc < 8; ++xc) A.rmax[A.slot_next * RM_SLOT + xc * RM_STRIDE] = 0ull;
+    if (v0 != T(0)) Lg[L_MSRC] += (double)v0;
+    if (v1 != T(0)) Lg[L_MSRC + 1] += (double)v1;
+    if (vd != 0.0) Lg[L_VDV] += vd;
+#pragma unroll
+    for (int kk = 0; kk < NS; ++kk) {
+      if (vs[kk] != T(0)) Lg[L_SSRC + kk] += (double)vs[kk];
+      if (vh[kk] != T(0)) Lg[L_SHET + kk] += (double)vh[kk];
     }
   }
-  __syncthreads();
-  if (ty == 0) {
-    double* L = A.led + (long long)tile * NLED;
-    if (tx == 0) {
-      double m = 0.0;
-      for (int w = 0; w < BY; ++w) m = fmax(m, s_rmax[w]);
-      if (m > 0.0) atomicMax(&A.rmax[A.slot_cur], (unsigned long long)__double_as_longlong(m));
-      if (bid == 0) A.rmax[A.slot_next] = 0ull;
-    }
-    // lane -> ledger slot
-    int src = -1, dst = -1;
-    if (tx < 2) { src = tx; dst = L_MSRC + tx; }
-    else if (tx == 2) { src = 2; dst = L_VDV; }
-    else if (tx >= 3 && tx < 3 + NS) { src = 4 + (tx - 3); dst = L_SSRC + (tx - 3); }
-    else if (tx >= 3 + NS && tx < 3 + 2 * NS) { src = 4 + NSA + (tx - 3 - NS); dst = L_SHET + (tx - 3 - NS); }
-    if (src >= 0) {
-      double s = 0.0;
-      for (int w = 0; w < BY; ++w) s += s_red[w][src];
-      if (s != 0.0) L[dst] += s;
-    }
-    // rare balances accumulated in LDS
-    if (tx >= 32 && tx < 32 + NRARE_SLOTS) {
-      const int i = tx - 32;
-      const double s = s_rare[i];
-      if (s != 0.0) L[rare_dst(i)] += s;
-    }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  if (lane < NRARE_SLOTS) {
+    const double s = L.rare[lane];
+    if (s != 0.0) Lg[rare_dst(lane)] += s;
   }
 }
 
-
 // ---------------------------------------------------------------- ledger sum
-// Fixed-order sum of the per-tile balance records (one block, one field per thread).
-__global__ void k_ledger_sum(const double* led, int nblocks, double* out) {
+// Fixed-order sum of the per-item balance records (one block, one field per thread).
+__global__ void k_ledger_sum(const double* led, int nitems, double* out) {
   const int f = threadIdx.x;
   if (f >= NLED) return;
   double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += led[(long long)b * NLED + f];
+  for (int b = 0; b < nitems; ++b) s += led[(long long)b * NLED + f];
   out[f] = s;
 }
 
 // ---------------------------------------------------------------- host side
-constexpr int TY64 = 6;   // FP64 tile height: 64 x 8 threads
-constexpr int TY32 = 14;  // FP32 tile height: 64 x 16 threads
+constexpr int SEG_ROWS = 16;  // default rows per item (LBRX_SEG_ROWS overrides, 1..HMAX)
 
-using KFn = void (*)(const KArgs);
+template <typename T> using KFnT = void (*)(const KArgs<T>);
 
-template <typename T, int TY, bool EXPORT>
-KFn pick(int ns) {
+template <typename T, bool EXPORT>
+KFnT<T> pick(int ns) {
   switch (ns) {
-    case 0: return k_step<T, 0, TY, EXPORT>;
-    case 1: return k_step<T, 1, TY, EXPORT>;
-    case 2: return k_step<T, 2, TY, EXPORT>;
-    case 3: return k_step<T, 3, TY, EXPORT>;
-    case 4: return k_step<T, 4, TY, EXPORT>;
-    case 5: return k_step<T, 5, TY, EXPORT>;
-    case 6: return k_step<T, 6, TY, EXPORT>;
-    case 7: return k_step<T, 7, TY, EXPORT>;
-    default: return k_step<T, 8, TY, EXPORT>;
+    case 0: return k_step<T, 0, EXPORT>;
+    case 1: return k_step<T, 1, EXPORT>;
+    case 2: return k_step<T, 2, EXPORT>;
+    case 3: return k_step<T, 3, EXPORT>;
+    case 4: return k_step<T, 4, EXPORT>;
+    case 5: return k_step<T, 5, EXPORT>;
+    case 6: return k_step<T, 6, EXPORT>;
+    case 7: return k_step<T, 7, EXPORT>;
+    default: return k_step<T, 8, EXPORT>;
   }
 }
 
@@ -710,14 +1077,13 @@ thread_local std::string g_create_err;
 struct lbrx_ctx {
   KConst c{};
   int precision = LBRX_F64;
-  int ty = TY64;
   size_t esz = 8;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   int device = 0;
   void* f[2] = {nullptr, nullptr};
   void* g[2] = {nullptr, nullptr};
-  uint8_t* t[2] = {nullptr, nullptr};
+  uint32_t* t[2] = {nullptr, nullptr};
   double* V = nullptr;
   unsigned long long* rmax = nullptr;
   double* led = nullptr;
@@ -728,7 +1094,10 @@ struct lbrx_ctx {
   int64_t steps = 0;
   bool failed = false;
   std::string msg;
-  KFn step_fn = nullptr, export_fn = nullptr;
+  KT<double> kd{};
+  KT<float> kf{};
+  KFnT<double> step64 = nullptr, export64 = nullptr;
+  KFnT<float> step32 = nullptr, export32 = nullptr;
 };
 
 namespace {
@@ -784,6 +1153,14 @@ std::string validate(const lbrx_params* p) {
     if (!(h.k >= 0.0)) return "rate constants must be >= 0";
   }
   if (!p->node_type || !p->rho1 || !p->rho2) return "node_type, rho1 and rho2 are required";
+  {
+    // the kernels address each population array with 32-bit byte offsets
+    const unsigned long long pitch = ((unsigned long long)p->nx + 63) / 64 * 64;
+    const unsigned long long esz = p->precision == LBRX_F64 ? 8 : 4;
+    const unsigned long long np = 18ull > 5ull * p->n_species ? 18ull : 5ull * p->n_species;
+    if (np * pitch * (unsigned long long)p->ny * esz >= (1ull << 32))
+      return "lattice too large: a population array must stay below 4 GiB (use FP32 or fewer species)";
+  }
   if (ns > 0 && !p->C0) return "C0 is required when n_species > 0";
   const long long N = (long long)p->nx * p->ny;
   for (long long i = 0; i < N; ++i) {
@@ -800,7 +1177,7 @@ std::string validate(const lbrx_params* p) {
 }
 
 template <typename T>
-void fill_populations(const lbrx_params* p, const KConst& c, const std::vector<uint8_t>& tb,
+void fill_populations(const lbrx_params* p, const KConst& c, const std::vector<uint32_t>& tb,
                       std::vector<T>& f, std::vector<T>& g) {
   const int nx = p->nx, ny = p->ny, ns = p->n_species;
   const long long plane = c.plane;
@@ -810,26 +1187,29 @@ void fill_populations(const lbrx_params* p, const KConst& c, const std::vector<u
     for (int x = 0; x < nx; ++x) {
       const long long i = (long long)y * nx + x, d = (long long)y * c.pitch + x;
       if ((tb[d] & TB_T) != T_FLUID) continue;
+      // row-interleaved storage: population q of node (x, y) at (y * NP + q) * pitch + x
+      const long long rf = (long long)y * 18 * c.pitch + x, rg = (long long)y * 5 * ns * c.pitch + x;
       for (int a = 0; a < 9; ++a) {
-        f[a * plane + d] = T(w9(a) * p->rho1[i]);
-        f[(9 + a) * plane + d] = T(w9(a) * p->rho2[i]);
+        f[rf + (long long)a * c.pitch] = T(w9(a) * p->rho1[i]);
+        f[rf + (long long)(9 + a) * c.pitch] = T(w9(a) * p->rho2[i]);
       }
       if (tb[d] & TB_LIQ)
         for (int k = 0; k < ns; ++k)
-          for (int a = 0; a < 5; ++a) g[((long long)k * 5 + a) * plane + d] = T(c.J[k][a] * p->C0[(long long)k * nx * ny + i]);
+          for (int a = 0; a < 5; ++a)
+            g[rg + (long long)(k * 5 + a) * c.pitch] = T(c.J[k][a] * p->C0[(long long)k * nx * ny + i]);
     }
 }
 
-lbrx_status launch_step(lbrx_ctx* x) {
-  KArgs A{};
+template <typename T>
+void fill_args(lbrx_ctx* x, KArgs<T>& A, const KT<T>& kt) {
   A.c = x->c;
-  const int nxt = 1 - x->cur;
+  A.k = kt;
   A.f_in = x->f[x->cur];
-  A.f_out = x->f[nxt];
   A.g_in = x->g[x->cur];
-  A.g_out = x->g[nxt];
   A.t_in = x->t[x->cur];
-  A.t_out = x->t[nxt];
+  A.f_out = x->f[1 - x->cur];
+  A.g_out = x->g[1 - x->cur];
+  A.t_out = x->t[1 - x->cur];
   A.V = x->V;
   A.rmax = x->rmax;
   const int s = (int)(x->steps % 3);
@@ -838,12 +1218,71 @@ lbrx_status launch_step(lbrx_ctx* x) {
   A.slot_next = (s + 1) % 3;
   A.led = x->led;
   A.err = x->err;
-  dim3 block(64, x->ty + 2);
-  hipLaunchKernelGGL(x->step_fn, dim3(x->c.nblocks), block, 0, x->stream, A);
+}
+
+lbrx_status launch_step(lbrx_ctx* x) {
+  const dim3 grid(x->c.nblocks), block(64, WPB);
+  if (x->precision == LBRX_F64) {
+    KArgs<double> A{};
+    fill_args(x, A, x->kd);
+    hipLaunchKernelGGL(x->step64, grid, block, 0, x->stream, A);
+  } else {
+    KArgs<float> A{};
+    fill_args(x, A, x->kf);
+    hipLaunchKernelGGL(x->step32, grid, block, 0, x->stream, A);
+  }
   HIPCHK(x, hipGetLastError());
-  x->cur = nxt;
+  x->cur = 1 - x->cur;
   x->steps += 1;
   return LBRX_OK;
+}
+
+template <typename T>
+void fill_kt(KT<T>& k, const lbrx_params* p, const KConst& c, const double* D) {
+  for (int s = 0; s < 2; ++s) {
+    k.om[s] = (T)c.om[s];
+    k.tau[s] = (T)p->tau[s];
+    k.r_tau[s] = (T)(1.0 / p->tau[s]);
+  }
+  k.RT = (T)c.RT;
+  k.a = (T)c.a;
+  k.b = (T)c.b;
+  k.G11 = (T)c.G11;
+  k.r_G11 = (T)(c.G11 != 0.0 ? 1.0 / c.G11 : 0.0);
+  k.psi_pre = (T)c.psi_pre;
+  k.G12 = (T)c.G12;
+  k.G21 = (T)c.G21;
+  k.w1 = (T)c.w1;
+  k.w2 = (T)c.w2;
+  k.gx = (T)c.gx;
+  k.gy = (T)c.gy;
+  k.a0 = (T)c.a0;
+  k.rho10 = (T)c.rho10;
+  k.r_rho10 = (T)(c.rho10 > 0.0 ? 1.0 / c.rho10 : 0.0);
+  k.rho20 = (T)c.rho20;
+  k.r_rho20 = (T)(c.rho20 > 0.0 ? 1.0 / c.rho20 : 0.0);
+  for (int q = 0; q < LBRX_MAX_SPECIES; ++q) {
+    k.omg[q] = (T)c.omg[q];
+    for (int a = 0; a < 5; ++a) k.J[q][a] = (T)c.J[q][a];
+  }
+  for (int r = 0; r < LBRX_MAX_RXN; ++r) {
+    k.hk[r] = (T)c.hk[r];
+    k.hKeq[r] = (T)c.hKeq[r];
+    k.r_hKeq[r] = (T)(c.hKeq[r] != 0.0 ? 1.0 / c.hKeq[r] : 0.0);
+    k.hMgas[r] = (T)c.hMgas[r];
+    k.r_hMgas[r] = (T)(c.hMgas[r] != 0.0 ? 1.0 / c.hMgas[r] : 0.0);
+    k.xkap[r] = (T)c.xkap[r];
+    k.xCeq[r] = (T)c.xCeq[r];
+    for (int q = 0; q < LBRX_MAX_SPECIES; ++q) k.hnu[r][q] = T(0);
+    if (r < c.nhom) {
+      // reactants consumed, products formed (Eq. 27)
+      if (c.hre0[r] >= 0) k.hnu[r][c.hre0[r]] -= T(1);
+      if (c.hre1[r] >= 0) k.hnu[r][c.hre1[r]] -= T(1);
+      if (c.hpr0[r] >= 0) k.hnu[r][c.hpr0[r]] += T(1);
+      if (c.hpr1[r] >= 0) k.hnu[r][c.hpr1[r]] += T(1);
+    }
+  }
+  (void)D;
 }
 
 }  // namespace
@@ -886,11 +1325,19 @@ lbrx_status lbrx_create(const lbrx_params* p, void* hip_stream, lbrx_ctx** out) 
   c.plane = (long long)c.pitch * p->ny;
   c.ns = p->n_species;
   x->precision = p->precision;
-  x->ty = p->precision == LBRX_F64 ? TY64 : TY32;
   x->esz = p->precision == LBRX_F64 ? 8 : 4;
-  c.tiles_x = (p->nx + TW - 1) / TW;
-  c.tiles_y = (p->ny + x->ty - 1) / x->ty;
-  c.nblocks = c.tiles_x * c.tiles_y;
+  c.seg_rows = SEG_ROWS;
+  if (const char* e = getenv("LBRX_SEG_ROWS")) {
+    const int v = atoi(e);
+    if (v >= 1 && v <= HMAX) c.seg_rows = v;
+  }
+  c.strips = c.pitch / SW;
+  c.nitems = c.strips * ((p->ny + c.seg_rows - 1) / c.seg_rows);
+  c.nblocks = (c.nitems + WPB - 1) / WPB;
+  // byte sizes of the population and status arrays (below 4 GiB, checked in validate)
+  c.fbytes = (unsigned)(18ull * (unsigned long long)c.plane * x->esz);
+  c.gbytes = (unsigned)((5ull * c.ns * (unsigned long long)c.plane + 1) * x->esz);
+  c.tbytes = (unsigned)((unsigned long long)c.plane * 4ull);
   for (int s = 0; s < 2; ++s) {
     c.tau[s] = p->tau[s];
     c.om[s] = 1.0 / p->tau[s];
@@ -945,8 +1392,12 @@ lbrx_status lbrx_create(const lbrx_params* p, void* hip_stream, lbrx_ctx** out) 
     c.xCeq[r] = h.C_eq;
     c.xmvol[r] = h.molar_volume;
   }
-  x->step_fn = p->precision == LBRX_F64 ? pick<double, TY64, false>(c.ns) : pick<float, TY32, false>(c.ns);
-  x->export_fn = p->precision == LBRX_F64 ? pick<double, TY64, true>(c.ns) : pick<float, TY32, true>(c.ns);
+  fill_kt(x->kd, p, c, D);
+  fill_kt(x->kf, p, c, D);
+  x->step64 = pick<double, false>(c.ns);
+  x->export64 = pick<double, true>(c.ns);
+  x->step32 = pick<float, false>(c.ns);
+  x->export32 = pick<float, true>(c.ns);
 
   auto fail = [&](lbrx_status s, const std::string& m) {
     g_create_err = m;
@@ -965,11 +1416,11 @@ lbrx_status lbrx_create(const lbrx_params* p, void* hip_stream, lbrx_ctx** out) 
   const size_t fbytes = 18 * plane * x->esz, gbytes = (5 * (size_t)c.ns * plane + 1) * x->esz;
   for (int i = 0; i < 2; ++i) {
     if (hipMalloc(&x->f[i], fbytes) != hipSuccess || hipMalloc(&x->g[i], gbytes) != hipSuccess ||
-        hipMalloc((void**)&x->t[i], plane) != hipSuccess)
+        hipMalloc((void**)&x->t[i], plane * 4) != hipSuccess)
       return fail(LBRX_E_NOMEM, "device allocation of the populations failed");
   }
-  if (hipMalloc((void**)&x->V, plane * 8) != hipSuccess || hipMalloc((void**)&x->rmax, 3 * 8) != hipSuccess ||
-      hipMalloc((void**)&x->led, (size_t)c.nblocks * NLED * 8) != hipSuccess ||
+  if (hipMalloc((void**)&x->V, plane * 8) != hipSuccess || hipMalloc((void**)&x->rmax, RM_WORDS * 8) != hipSuccess ||
+      hipMalloc((void**)&x->led, (size_t)c.nitems * NLED * 8) != hipSuccess ||
       hipMalloc((void**)&x->ledsum, NLED * 8) != hipSuccess || hipMalloc((void**)&x->err, 2 * 4) != hipSuccess)
     return fail(LBRX_E_NOMEM, "device allocation of the state failed");
 
@@ -979,13 +1430,15 @@ lbrx_status lbrx_create(const lbrx_params* p, void* hip_stream, lbrx_ctx** out) 
   for (long long i = 0; i < (long long)nx * ny; ++i)
     if (p->node_type[i] == LBRX_FLUID && p->rho1[i] > rmax0) rmax0 = p->rho1[i];
   const double thr0 = p->liquid_frac * rmax0;
-  std::vector<uint8_t> tb(plane, (uint8_t)T_INERT);
+  std::vector<uint32_t> tb(plane, (uint32_t)T_INERT);
   std::vector<double> V(plane, 0.0);
   for (int y = 0; y < ny; ++y)
     for (int xx = 0; xx < nx; ++xx) {
       const long long i = (long long)y * nx + xx, d = (long long)y * c.pitch + xx;
       const uint8_t t = p->node_type[i];
-      uint8_t b = t;
+      uint32_t b = t;
+      // step 0: no neighbour bits, so every node reads its own slots, which
+      // hold f(0) (and g(0) at liquid nodes)
       if (t == LBRX_FLUID && p->rho1[i] > thr0) b |= TB_LIQ | TB_LIQP;
       tb[d] = b;
       V[d] = p->V0 ? p->V0[i] : ((t == LBRX_SOLID_D || t == LBRX_SOLID_F) ? 1.0 : 0.0);
@@ -1005,15 +1458,15 @@ lbrx_status lbrx_create(const lbrx_params* p, void* hip_stream, lbrx_ctx** out) 
   // the second buffers start as copies so that never-written slots hold defined values
   if (e == hipSuccess) e = hipMemcpy(x->f[1], x->f[0], fbytes, hipMemcpyDeviceToDevice);
   if (e == hipSuccess) e = hipMemcpy(x->g[1], x->g[0], gbytes, hipMemcpyDeviceToDevice);
-  if (e == hipSuccess) e = hipMemcpy(x->t[0], tb.data(), plane, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(x->t[1], tb.data(), plane, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(x->t[0], tb.data(), plane * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(x->t[1], tb.data(), plane * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(x->V, V.data(), plane * 8, hipMemcpyHostToDevice);
-  unsigned long long rm[3] = {0ull, 0ull, 0ull};
-  std::memcpy(&rm[2], &rmax0, 8);
-  if (e == hipSuccess) e = hipMemcpy(x->rmax, rm, sizeof rm, hipMemcpyHostToDevice);
+  std::vector<unsigned long long> rm(RM_WORDS, 0ull);
+  std::memcpy(&rm[2 * RM_SLOT], &rmax0, 8);  // the "previous step" of step 0
+  if (e == hipSuccess) e = hipMemcpy(x->rmax, rm.data(), RM_WORDS * 8, hipMemcpyHostToDevice);
   unsigned int er[2] = {0u, 0xffffffffu};
   if (e == hipSuccess) e = hipMemcpy(x->err, er, sizeof er, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemset(x->led, 0, (size_t)c.nblocks * NLED * 8);
+  if (e == hipSuccess) e = hipMemset(x->led, 0, (size_t)c.nitems * NLED * 8);
   if (e != hipSuccess) return fail(LBRX_E_DEVICE, std::string("initial copy failed: ") + hipGetErrorString(e));
   *out = x;
   return LBRX_OK;
@@ -1057,26 +1510,28 @@ lbrx_status lbrx_fields(lbrx_ctx* x, lbrx_fields_out* o) {
   const size_t plane = (size_t)c.plane;
   if (!x->out) HIPCHK(x, hipMalloc((void**)&x->out, (4 + (size_t)c.ns) * plane * 8));
   HIPCHK(x, hipMemsetAsync(x->out, 0, (4 + (size_t)c.ns) * plane * 8, x->stream));
-  KArgs A{};
-  A.c = c;
-  A.f_in = x->f[x->cur];
-  A.g_in = x->g[x->cur];
-  A.t_in = x->t[x->cur];
-  A.V = x->V;
-  A.rmax = x->rmax;
-  const int s = (int)(x->steps % 3);
-  A.slot_prev = (s + 2) % 3;
-  A.slot_cur = s;
-  A.slot_next = (s + 1) % 3;
-  A.err = x->err;
-  A.o_r1 = x->out;
-  A.o_r2 = x->out + plane;
-  A.o_ux = x->out + 2 * plane;
-  A.o_uy = x->out + 3 * plane;
-  A.o_C = x->out + 4 * plane;
-  hipLaunchKernelGGL(x->export_fn, dim3(c.nblocks), dim3(64, x->ty + 2), 0, x->stream, A);
+  const dim3 grid(c.nblocks), block(64, WPB);
+  if (x->precision == LBRX_F64) {
+    KArgs<double> A{};
+    fill_args(x, A, x->kd);
+    A.o_r1 = x->out;
+    A.o_r2 = x->out + plane;
+    A.o_ux = x->out + 2 * plane;
+    A.o_uy = x->out + 3 * plane;
+    A.o_C = x->out + 4 * plane;
+    hipLaunchKernelGGL(x->export64, grid, block, 0, x->stream, A);
+  } else {
+    KArgs<float> A{};
+    fill_args(x, A, x->kf);
+    A.o_r1 = x->out;
+    A.o_r2 = x->out + plane;
+    A.o_ux = x->out + 2 * plane;
+    A.o_uy = x->out + 3 * plane;
+    A.o_C = x->out + 4 * plane;
+    hipLaunchKernelGGL(x->export32, grid, block, 0, x->stream, A);
+  }
   HIPCHK(x, hipGetLastError());
-  hipLaunchKernelGGL(k_ledger_sum, dim3(1), dim3(64), 0, x->stream, x->led, c.nblocks, x->ledsum);
+  hipLaunchKernelGGL(k_ledger_sum, dim3(1), dim3(64), 0, x->stream, x->led, c.nitems, x->ledsum);
   HIPCHK(x, hipGetLastError());
   HIPCHK(x, hipStreamSynchronize(x->stream));
   const size_t sp = (size_t)c.pitch * 8, dp = (size_t)c.nx * 8;
@@ -1091,8 +1546,9 @@ lbrx_status lbrx_fields(lbrx_ctx* x, lbrx_fields_out* o) {
     for (int k = 0; k < c.ns; ++k) HIPCHK(x, get2d(o->C + (size_t)k * c.nx * c.ny, x->out + (4 + k) * plane));
   if (o->V) HIPCHK(x, get2d(o->V, x->V));
   if (o->type || o->liquid) {
-    std::vector<uint8_t> tb((size_t)c.nx * c.ny);
-    HIPCHK(x, hipMemcpy2D(tb.data(), c.nx, x->t[x->cur], c.pitch, c.nx, c.ny, hipMemcpyDeviceToHost));
+    std::vector<uint32_t> tb((size_t)c.nx * c.ny);
+    HIPCHK(x, hipMemcpy2D(tb.data(), (size_t)c.nx * 4, x->t[x->cur], (size_t)c.pitch * 4, (size_t)c.nx * 4, c.ny,
+                          hipMemcpyDeviceToHost));
     for (size_t i = 0; i < tb.size(); ++i) {
       if (o->type) o->type[i] = tb[i] & TB_T;
       if (o->liquid) o->liquid[i] = (tb[i] & TB_LIQ) ? 1 : 0;
@@ -1106,10 +1562,16 @@ lbrx_status lbrx_fields(lbrx_ctx* x, lbrx_fields_out* o) {
     std::memcpy(o->ledger, l, sizeof l);
   }
   if (o->rho_max) {
-    unsigned long long v;
+    std::vector<unsigned long long> v(RM_WORDS);
     const int last = (int)((x->steps + 2) % 3);
-    HIPCHK(x, hipMemcpy(&v, x->rmax + last, 8, hipMemcpyDeviceToHost));
-    std::memcpy(o->rho_max, &v, 8);
+    HIPCHK(x, hipMemcpy(v.data(), x->rmax, RM_WORDS * 8, hipMemcpyDeviceToHost));
+    double m = 0.0;
+    for (int xc = 0; xc < 8; ++xc) {
+      double d;
+      std::memcpy(&d, &v[last * RM_SLOT + xc * RM_STRIDE], 8);
+      m = d > m ? d : m;
+    }
+    *o->rho_max = m;
   }
   return LBRX_OK;
 }
