@@ -58,6 +58,22 @@ def algorithmic_bytes(F, prob, esz):
     return b, counts
 
 
+def measured_traffic(precision, n):
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
+    summary (calibrated FETCH_SIZE + WRITE_SIZE), or None when there is none for
+    this precision and size or the kernel source has changed since."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"k_step_{precision}_porous{n}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, rec["kernel_source"]), "rb").read()
+    if hashlib.sha256(src).hexdigest() != rec["kernel_source_sha256"]:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def cpu_baseline(prob, steps):
     """The FP64 oracle, as it stands, single-threaded on the host: `steps` steps of
     the same lattice."""
@@ -84,8 +100,6 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe-gb", type=float, default=0.0,
                     help="run a plain device-to-device copy of this many GB first (counter calibration)")
-    ap.add_argument("--traffic-gb", type=float, default=None,
-                    help="HBM GB per launch measured by rocprofv3 counters for this kernel build")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -145,6 +159,7 @@ def main():
     n = prob.nx * prob.ny
     mlups = n * args.steps / wall / 1e6
     achieved = b_alg / (kern_ms * 1e-3) / 1e9
+    traffic = measured_traffic(args.precision, args.size)
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -172,7 +187,9 @@ def main():
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4),
-            "traffic": None if args.traffic_gb is None else args.traffic_gb,
+            "traffic": None if traffic is None else round(traffic / 1e9, 4),
+            "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE x 1, copy-calibrated)",
+            "traffic_gbs": None if traffic is None else round(traffic / (kern_ms * 1e-3) / 1e9, 1),
             "kernel_ms": round(kern_ms, 4),
             "alg_bytes_per_launch": int(b_alg),
         },

@@ -5,7 +5,9 @@ paper prints, closed-form solutions of the continuum equations the lattice
 models recover, and exact invariants of the scheme.  A dropped term, a wrong
 sign or a transposed index in the oracle fails at least one of them.
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -57,16 +59,17 @@ def _flat_interface(eos, Tr, rl, rv, psi_literal=False, ny=128, steps=16000):
     return F["rho1"][ny // 2, 0], F["rho1"][0, 0], np.abs(F["uy"]).max()
 
 
-@pytest.mark.parametrize("eos,Tr,liq_paper,vap_paper", [
-    (W.EOS_ORIGINAL, 0.70, 0.3589, 0.00670),   # values printed after Eq. 13
-    (W.EOS_PAPER, 0.70, 7.739, 0.17),          # values printed after Eq. 13
-    (W.EOS_PAPER, 0.65, 8.17, None),           # liquid density of Sec. 5.1
-])
-def test_coexistence_densities_match_paper(eos, Tr, liq_paper, vap_paper):
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_printed_values.json")))
+
+
+@pytest.mark.parametrize("case", GOLDEN["coexistence"], ids=lambda c: f"{c['eos']}-{c['T_over_Tc']}")
+def test_coexistence_densities_match_paper(case):
     """A flat interface relaxes to the liquid density the paper prints within 2%
     (the vapour branch of a pseudopotential fluid departs from Maxwell; within 25%).
     This pins the psi prefactor: with the stencil weights 1/3 and 1/12 of Eq. 11,
     psi = sqrt(2 (p - rho/3)/G11) reproduces the EOS of Eq. 12."""
+    eos = (case["a"], case["b"], case["R"])
+    Tr, liq_paper, vap_paper = case["T_over_Tc"], case["rho_liquid"], case["rho_vapour"]
     rl, rv, _ = _maxwell(*eos, Tr)
     liq, vap, umax = _flat_interface(eos, Tr, rl, rv)
     assert abs(liq / liq_paper - 1) < 0.02
@@ -114,10 +117,11 @@ def test_workload_coexistence_constants():
     assert abs(rl - W.RHO_L_075) < 1e-8 and abs(rv - W.RHO_V_075) < 1e-8
     rl, rv, _ = _maxwell(*W.EOS_PAPER, 0.75)
     assert abs(rl - W.RHO_L_075_PAPER) < 1e-7 and abs(rv - W.RHO_V_075_PAPER) < 1e-8
-    # T_c of the original set is printed as 0.094 after Eq. 13
-    assert abs(W.critical_temperature(*W.EOS_ORIGINAL) - 0.094) < 5e-4
+    # T_c of the original set as printed after Eq. 13
+    assert abs(W.critical_temperature(*W.EOS_ORIGINAL) - GOLDEN["critical_temperature_original"]["value"]) < 5e-4
     # rho_10 uses the natural logarithm: phi_2 changes sign at rho_1 = 0.008
-    assert abs(0.005 - math.exp(-0.008 / W.paper_rho10(0.005))) < 1e-15
+    z = GOLDEN["rho10_zero_crossing"]
+    assert abs(z["a0"] - math.exp(-z["rho1"] / W.paper_rho10(z["a0"]))) < 1e-15
 
 
 # --------------------------------------------------------------------------
