@@ -30,7 +30,8 @@ def algorithmic_bytes(F, prob, esz):
     """Bytes one step must move at minimum: every flow population of a fluid node
     read and written once, every solute population of a liquid node read and
     written once, the node-type byte read and written, and the FP64 solid /
-    precipitate volume read and written at liquid-solid interface nodes."""
+    precipitate volume read and written at liquid-solid interface nodes (with
+    16-bit storage also the solute reference codes of liquid nodes)."""
     t = F["type"]
     fluid = t == 0
     liq = F["liquid"].astype(bool)
@@ -54,6 +55,9 @@ def algorithmic_bytes(F, prob, esz):
     interface = (reactive & near_liq) | (liq & near_rs)
     n = t.size
     b = (int(fluid.sum()) * 36 * esz + int(liq.sum()) * 10 * ns * esz + 2 * n + 16 * int(interface.sum()))
+    if esz == 2 and ns > 0:
+        # 16-bit storage: the solute reference codes, one 32-bit word per four species, read and written
+        b += int(liq.sum()) * 8 * ((ns + 3) // 4)
     counts = dict(fluid=int(fluid.sum()), liquid=int(liq.sum()), interface=int(interface.sum()), nodes=n)
     return b, counts
 
@@ -94,7 +98,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=30)
-    ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--precision", default="f32", choices=["f32", "f64", "f16dev", "bf16dev"])
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
@@ -130,7 +134,7 @@ def main():
     # timing events are recorded on it
     stream = torch.cuda.Stream()
     sim = Lbrx(prob, args.precision, stream=stream.cuda_stream)
-    esz = 4 if args.precision == "f32" else 8
+    esz = {"f64": 8, "f32": 4, "f16dev": 2, "bf16dev": 2}[args.precision]
 
     sim.step(args.warmup)
     sim.sync()

@@ -47,8 +47,15 @@ typedef enum {
 } lbrx_status;
 
 /* Storage and arithmetic precision of the populations.  Solid volumes and the
- * balance ledger are FP64 in every mode. */
-typedef enum { LBRX_F64 = 0, LBRX_F32 = 1 } lbrx_precision;
+ * balance ledger are FP64 in every mode.
+ *   LBRX_F64, LBRX_F32: populations stored and updated in that precision.
+ *   LBRX_F16DEV, LBRX_BF16DEV: populations stored as 16-bit (IEEE half or
+ *     bfloat16) deviations from their equilibrium at rest for a coded
+ *     reference density (concentration) of the node that reads them, times a
+ *     power-of-two scale; all arithmetic in FP32.  Half the population bytes
+ *     of LBRX_F32; the accuracy against FP64 is stated per field in the
+ *     design notes. */
+typedef enum { LBRX_F64 = 0, LBRX_F32 = 1, LBRX_F16DEV = 2, LBRX_BF16DEV = 3 } lbrx_precision;
 
 /* node types (Fig. 2): fluid, inert solid, dissolvable solid D(s), precipitate F(s) */
 enum { LBRX_FLUID = 0, LBRX_SOLID_INERT = 1, LBRX_SOLID_D = 2, LBRX_SOLID_F = 3 };

@@ -24,6 +24,7 @@
 //     FP64 record per item (no floating-point atomics in global memory).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 #include <cstdint>
@@ -59,6 +60,34 @@ static_assert(opp(5) == 7 && opp(6) == 8 && opp(7) == 5 && opp(8) == 6, "opp dia
 // Bit 7 marks "outside a non-periodic boundary" in the kernel only.
 constexpr uint32_t TB_T = 0x3, TB_LIQ = 0x4, TB_LIQP = 0x8, TB_STR = 0x10, TB_WALL = 0x80;
 constexpr int NBF_SHIFT = 8, NBL_SHIFT = 16;
+
+// 16-bit population storage keeps each population as a deviation from w_a
+// times a reference density of the node that will pull it (flow) or J_a
+// times a reference concentration (solute).  A reference is coded in a few
+// bits: the float's bit pattern above bit `sh` (exponent and top mantissa
+// bits), counted from a base, and decoded to the middle of its bucket.  The
+// codes are integer operations on both sides, so the writer of a population
+// and its reader always agree on the reference.  The flow codes of a node
+// (rho_1: 8 bits, rho_2: 7 bits) ride in bits 24-31 and 20-23, 5-7 of its
+// status word; the solute codes (8 bits per species) in one 32-bit word per
+// four species.
+constexpr int SH1 = 19, SH2 = 20, SHC = 19;  // 16, 16 and 16 binades of range
+constexpr uint32_t MAX1 = 255, MAX2 = 127, MAXC = 255;
+__host__ __device__ inline uint32_t ref_code(float v, uint32_t base, int sh, uint32_t maxc) {
+  const uint32_t b = __builtin_bit_cast(uint32_t, v);
+  if (b == 0u || (b >> 31)) return 0u;  // zero or negative: the lowest reference
+  const uint32_t q = b >> sh;
+  if (q <= base) return 0u;
+  return (q - base) < maxc ? (q - base) : maxc;
+}
+__host__ __device__ inline float ref_value(uint32_t code, uint32_t base, int sh) {
+  return __builtin_bit_cast(float, ((code + base) << sh) | (1u << (sh - 1)));
+}
+__host__ __device__ inline uint32_t put_codes(uint32_t c1, uint32_t c2) {
+  return (c1 << 24) | ((c2 & 15u) << 20) | ((c2 >> 4) << 5);
+}
+__host__ __device__ inline uint32_t code1_of(uint32_t w) { return w >> 24; }
+__host__ __device__ inline uint32_t code2_of(uint32_t w) { return ((w >> 20) & 15u) | (((w >> 5) & 7u) << 4); }
 constexpr int T_FLUID = 0, T_INERT = 1, T_D = 2, T_F = 3;
 
 
@@ -86,7 +115,8 @@ enum { HET_CONSUMES = 0, HET_GROWS = 1, HET_MINERAL = 2 };
 
 struct KConst {
   int nx, ny, pitch, per_x, per_y, strips, seg_rows, nitems, nblocks, ns;
-  unsigned fbytes, gbytes, tbytes;  // array sizes (buffer ranges)
+  unsigned fbytes, gbytes, tbytes, cbytes;  // array sizes (buffer ranges)
+  int ncw;                                  // solute code words per node (16-bit storage)
   long long plane;
   double om[2], tau[2], RT, a, b, G11, psi_pre, G12, G21, w1, w2, gx, gy, a0, rho10, rho20, lfrac;
   int has_psi, has_phi1, has_phi2;
@@ -110,6 +140,11 @@ template <typename T> struct KT {
   T hk[LBRX_MAX_RXN], hKeq[LBRX_MAX_RXN], r_hKeq[LBRX_MAX_RXN], hMgas[LBRX_MAX_RXN], r_hMgas[LBRX_MAX_RXN];
   T xkap[LBRX_MAX_RXN], xCeq[LBRX_MAX_RXN];
   T hnu[LBRX_MAX_RXN][LBRX_MAX_SPECIES];  // net stoichiometric coefficient of species k in reaction r
+  // 16-bit storage: deviation scales (powers of two) and reference-code bases
+  T sc[2], isc[2], wsc[2][3];               // flow: scale, 1/scale, w (rest, axis, diagonal) x scale
+  T scg[LBRX_MAX_SPECIES], iscg[LBRX_MAX_SPECIES], Jsc[LBRX_MAX_SPECIES][2];
+  T wc[3], Jc[LBRX_MAX_SPECIES][2];         // the weights themselves
+  uint32_t rb1, rb2, rbc[LBRX_MAX_SPECIES];
 };
 
 template <typename T> struct KArgs {
@@ -121,6 +156,8 @@ template <typename T> struct KArgs {
   void* g_out;
   const uint32_t* t_in;
   uint32_t* t_out;
+  const uint32_t* c_in;  // solute reference codes (16-bit storage)
+  uint32_t* c_out;
   double* V;
   unsigned long long* rmax;  // 3 rotating slots
   int slot_prev, slot_cur, slot_next;
@@ -255,16 +292,43 @@ template <typename T> __device__ inline uint32_t flags_of(T v) {
   else return (uint32_t)__builtin_bit_cast(unsigned long long, v);
 }
 
-template <typename T, int NS> struct WaveLds {
+// Population storage: the working precision itself, or 16-bit deviations
+// (FP16 or BF16, with FP32 arithmetic) from the coded references above.
+enum { SM_PLAIN = 0, SM_F16 = 1, SM_BF16 = 2 };
+template <typename T, int SM> struct StoreT { using type = T; };
+template <> struct StoreT<float, SM_F16> { using type = uint16_t; };
+template <> struct StoreT<float, SM_BF16> { using type = uint16_t; };
+template <int SM> __device__ inline float dev_in(uint16_t h) {
+  if constexpr (SM == SM_F16) return (float)__builtin_bit_cast(_Float16, h);
+  else return __builtin_bit_cast(float, (uint32_t)h << 16);
+}
+template <int SM> __device__ inline uint16_t dev_out(float v) {
+  if constexpr (SM == SM_F16) return __builtin_bit_cast(uint16_t, (_Float16)v);
+  else return __builtin_bit_cast(uint16_t, (__bf16)v);
+}
+// weight class of a direction: rest, axis, diagonal
+__host__ __device__ constexpr int wcls(int a) { return a == 0 ? 0 : (a < 5 ? 1 : 2); }
+
+template <typename T> struct alignas(2 * sizeof(T)) RF {
+  T r1, r2;  // reference densities a population written to this node is coded against
+};
+
+template <typename T, int NS, int SM> struct WaveLds {
   static constexpr int NSA = NS > 0 ? NS : 1;
+  static constexpr int NRF = SM != SM_PLAIN ? 3 : 1;  // reference rows (16-bit storage only)
+  static constexpr int NHF = SM != SM_PLAIN ? 2 : 1;
   // ring rows (R - 1, R, R + 1 in rotation) x columns x0 - 1 .. x0 + 64
   PQ<T> pq[3][SW + 2];
   T r1[3][SW + 2], r2[3][SW + 2];
   T C[NSA][3][SW + 2];
+  RF<T> rf[NRF][SW + 2];
+  T Cf[NSA][NRF][SW + 2];
   // halo columns (left, right) for rows y0 - 1 .. y0 + H
   PQ<T> hpq[2][HMAX + 2];
   T hr1[2][HMAX + 2], hr2[2][HMAX + 2];
   T hC[NSA][2][HMAX + 2];
+  RF<T> hrf[NHF][HMAX + 2];
+  T hCf[NSA][NHF][HMAX + 2];
   double rare[NRARE_SLOTS];
 };
 
@@ -274,19 +338,59 @@ __device__ inline __amdgpu_buffer_rsrc_t rsrc_of(const void* p, unsigned bytes) 
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
 }
 template <typename T> __device__ inline T bload(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
-  if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0));
+  if constexpr (sizeof(T) == 2) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, (int)so, 0));
+  else if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0));
   else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0));
 }
+// Stores are non-temporal (cache policy bit "nt"): nothing reads the written
+// lines in the same launch, and keeping them out of the way leaves the L2 to
+// the rows the pulls of neighbouring rows read again.
+constexpr int STORE_NT = 2;
 template <typename T> __device__ inline void bstore(T v, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
-  if constexpr (sizeof(T) == 4) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)vo, (int)so, 0);
-  else __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u_t, v), r, (int)vo, (int)so, 0);
+  if constexpr (sizeof(T) == 2) __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, (int)vo, (int)so, STORE_NT);
+  else if constexpr (sizeof(T) == 4) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)vo, (int)so, STORE_NT);
+  else __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u_t, v), r, (int)vo, (int)so, STORE_NT);
+}
+
+// Slots hold pairs: both flow components of one direction, or two species of
+// one direction, so that one load or store moves both (16-bit pairs make one
+// 32-bit word per lane).
+template <typename ST> struct Pair {
+  ST lo, hi;
+};
+typedef unsigned int v4u_t __attribute__((ext_vector_type(4)));
+template <typename ST> __device__ inline Pair<ST> bload2(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+  if constexpr (sizeof(ST) == 2) {
+    const uint32_t u = __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0);
+    return Pair<ST>{(ST)(u & 0xffffu), (ST)(u >> 16)};
+  } else {
+    // The loaded vector is reinterpreted as a whole (two-element vector of
+    // ST): taking its integer elements apart one by one let the compiler
+    // shrink the load to the low dword.
+    typedef ST v2s_t __attribute__((ext_vector_type(2)));
+    v2s_t u;
+    if constexpr (sizeof(ST) == 4) u = __builtin_bit_cast(v2s_t, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0));
+    else u = __builtin_bit_cast(v2s_t, __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, 0));
+    return Pair<ST>{u.x, u.y};
+  }
+}
+template <typename ST> __device__ inline void bstore2(ST lo, ST hi, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+  if constexpr (sizeof(ST) == 2) {
+    __builtin_amdgcn_raw_buffer_store_b32((uint32_t)lo | ((uint32_t)hi << 16), r, (int)vo, (int)so, STORE_NT);
+  } else if constexpr (sizeof(ST) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b64(v2u_t{__builtin_bit_cast(uint32_t, lo), __builtin_bit_cast(uint32_t, hi)}, r,
+                                          (int)vo, (int)so, STORE_NT);
+  } else {
+    const v2u_t a = __builtin_bit_cast(v2u_t, lo), b = __builtin_bit_cast(v2u_t, hi);
+    __builtin_amdgcn_raw_buffer_store_b128(v4u_t{a.x, a.y, b.x, b.y}, r, (int)vo, (int)so, STORE_NT);
+  }
 }
 
 template <typename T, int NS> struct Mom {
   T rho[2], jx[2], jy[2], C[NS > 0 ? NS : 1];
 };
 
-template <typename T, int NS, bool EXPORT>
+template <typename T, int SM, int NS, bool EXPORT>
 __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const KArgs<T> A_arg) {
   // The arguments are read where the launch put them (the kernarg segment, a
   // constant address space): the helpers below refer to them, and a reference
@@ -295,12 +399,14 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const KArgs<T
   (void)A_arg;
   const KArgs<T>& A = *(const KArgs<T>*)__builtin_amdgcn_kernarg_segment_ptr();
   constexpr int NSA = NS > 0 ? NS : 1;
-  constexpr unsigned ES = sizeof(T);
-  constexpr unsigned NPG = 5 * NS;
+  using ST = typename StoreT<T, SM>::type;  // stored population type
+  constexpr unsigned ES = sizeof(ST);
+  constexpr bool DEV = SM != SM_PLAIN;
+  static_assert(!DEV || std::is_same<T, float>::value, "16-bit storage computes in FP32");
   const KConst& c = A.c;
   const KT<T>& k = A.k;
-  __shared__ WaveLds<T, NS> s_all[WPB];
-  WaveLds<T, NS>& L = s_all[threadIdx.y];
+  __shared__ WaveLds<T, NS, SM> s_all[WPB];
+  WaveLds<T, NS, SM>& L = s_all[threadIdx.y];
   const int lane = threadIdx.x;
 
   // XCD-aware order: consecutive workgroups are dealt round-robin to the 8
@@ -318,13 +424,17 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const KArgs<T
   const int nrow = y1 - y0;
   const int nx = c.nx, ny = c.ny;
   const unsigned upitch = (unsigned)c.pitch;
-  const unsigned PS = upitch * ES;     // bytes per population plane row
-  const unsigned RSF = 18u * PS;       // bytes per lattice row, flow populations
-  const unsigned RSG = NPG * PS;       // bytes per lattice row, solute populations
+  constexpr int NSP = (NS + 1) / 2;    // species pairs
+  constexpr unsigned PE = 2 * ES;      // bytes per slot (a pair)
+  const unsigned PS = upitch * PE;     // bytes per slot plane row
+  const unsigned RSF = 9u * PS;        // bytes per lattice row, flow: 9 directions x (component 1, 2)
+  const unsigned RSG = 5u * NSP * PS;  // bytes per lattice row, solute: species pairs x 5 directions
 
   const __amdgpu_buffer_rsrc_t rf = rsrc_of(A.f_in, c.fbytes);
   const __amdgpu_buffer_rsrc_t rg = rsrc_of(A.g_in, c.gbytes);
   const __amdgpu_buffer_rsrc_t rt = rsrc_of(A.t_in, c.tbytes);
+  const __amdgpu_buffer_rsrc_t rcw = rsrc_of(A.c_in, c.cbytes);
+  const unsigned ncw = (unsigned)c.ncw;
 
   if (!EXPORT && lane < NRARE_SLOTS) L.rare[lane] = 0.0;
 
@@ -352,19 +462,35 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const KArgs<T
     if (ym < 0) ym += ny;
     if (yp >= ny) yp -= ny;
     const unsigned ur[3] = {(unsigned)ym, (unsigned)Yw, (unsigned)yp};
+    // a stored value becomes a population: itself, or (16-bit storage)
+    // deviation / scale + weight x this node's reference
+    T fb[2][3];
+    if constexpr (DEV) {
+      const T r1 = ref_value(code1_of(w), k.rb1, SH1), r2 = ref_value(code2_of(w), k.rb2, SH2);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        fb[0][q] = k.wc[q] * r1;
+        fb[1][q] = k.wc[q] * r2;
+      }
+    }
+    auto fin = [&](int a, unsigned vo) {
+      const Pair<ST> q = bload2<ST>(rf, vo, 0u);
+      if constexpr (DEV) {
+        f[0][a] = __builtin_fmaf(dev_in<SM>(q.lo), k.isc[0], fb[0][wcls(a)]);
+        f[1][a] = __builtin_fmaf(dev_in<SM>(q.hi), k.isc[1], fb[1][wcls(a)]);
+      } else {
+        f[0][a] = q.lo;
+        f[1][a] = q.hi;
+      }
+    };
     if (validf) {
       const unsigned own = co[1] + ur[1] * RSF;
-      f[0][0] = bload<T>(rf, own, 0);
-      f[1][0] = bload<T>(rf, own, 9 * PS);
+      fin(0, own);
 #pragma unroll
       for (int b = 1; b < 9; ++b) {
         const int a = opp(b);
         const bool src = (w >> (NBF_SHIFT + b - 1)) & 1u;
-        const unsigned vo = src ? co[ex(b) + 1] + (ur[ey(b) + 1] * RSF + (unsigned)a * PS) : own + (unsigned)b * PS;
-        const unsigned pa = src ? (unsigned)a : (unsigned)b;
-        (void)pa;
-        f[0][a] = bload<T>(rf, vo, 0);
-        f[1][a] = bload<T>(rf, vo, 9 * PS);
+        fin(a, src ? co[ex(b) + 1] + (ur[ey(b) + 1] * RSF + (unsigned)a * PS) : own + (unsigned)b * PS);
       }
     } else {
 #pragma unroll
@@ -374,15 +500,38 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const KArgs<T
     }
     if (NS > 0 && liqp) {
       const unsigned own = co[1] + ur[1] * RSG;
+      T gb[NSA][2];
+      if constexpr (DEV) {
+        // this node's solute reference codes, one word per four species
+        const unsigned cwo = (co[1] / PE) * 4u + ur[1] * ncw * upitch * 4u;
+        const uint32_t cw0 = bload<uint32_t>(rcw, cwo, 0u);
+        const uint32_t cw1 = NS > 4 ? bload<uint32_t>(rcw, cwo, upitch * 4u) : 0u;
 #pragma unroll
-      for (int kk = 0; kk < NS; ++kk) g[kk][0] = bload<T>(rg, own, (unsigned)(kk * 5) * PS);
+        for (int kk = 0; kk < NS; ++kk) {
+          const T cr = ref_value(((kk < 4 ? cw0 : cw1) >> (8 * (kk & 3))) & 255u, k.rbc[kk], SHC);
+          gb[kk][0] = k.Jc[kk][0] * cr;
+          gb[kk][1] = k.Jc[kk][1] * cr;
+        }
+      }
+      auto gcv = [&](int kk, int a, ST v) -> T {
+        if constexpr (DEV) return __builtin_fmaf(dev_in<SM>(v), k.iscg[kk], gb[kk][a == 0 ? 0 : 1]);
+        else return v;
+      };
+      // species pair j holds species 2j (low) and 2j + 1 (high)
+      auto gin = [&](int a, unsigned vo) {
+#pragma unroll
+        for (int j = 0; j < NSP; ++j) {
+          const Pair<ST> q = bload2<ST>(rg, vo, (unsigned)(j * 5) * PS);
+          g[2 * j][a] = gcv(2 * j, a, q.lo);
+          if (2 * j + 1 < NS) g[2 * j + 1][a] = gcv(2 * j + 1, a, q.hi);
+        }
+      };
+      gin(0, own);
 #pragma unroll
       for (int b = 1; b < 5; ++b) {
         const int a = opp(b);
         const bool src = (w >> (NBL_SHIFT + b - 1)) & 1u;
-        const unsigned vo = src ? co[ex(b) + 1] + (ur[ey(b) + 1] * RSG + (unsigned)a * PS) : own + (unsigned)b * PS;
-#pragma unroll
-        for (int kk = 0; kk < NS; ++kk) g[kk][a] = bload<T>(rg, vo, (unsigned)(kk * 5) * PS);
+        gin(a, src ? co[ex(b) + 1] + (ur[ey(b) + 1] * RSG + (unsigned)a * PS) : own + (unsigned)b * PS);
       }
     } else {
 #pragma unroll
@@ -435,13 +584,25 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const KArgs<T
     }
   };
 
+  // the references this node's populations are coded against when they are
+  // written this step (from the current moments; stored in its status and
+  // solute words for the reader)
+  auto wref = [&](const Mom<T, NS>& m, RF<T>& r, T(&cf)[NSA]) {
+    if constexpr (DEV) {
+      r.r1 = ref_value(ref_code(m.rho[0], k.rb1, SH1, MAX1), k.rb1, SH1);
+      r.r2 = ref_value(ref_code(m.rho[1], k.rb2, SH2, MAX2), k.rb2, SH2);
+#pragma unroll
+      for (int kk = 0; kk < NSA; ++kk) cf[kk] = ref_value(ref_code(m.C[kk], k.rbc[kk], SHC, MAXC), k.rbc[kk], SHC);
+    }
+  };
+
   auto col_offsets = [&](int Xw, unsigned (&co)[3]) {
     int xm = Xw - 1, xp = Xw + 1;
     if (xm < 0) xm += nx;
     if (xp >= nx) xp -= nx;
-    co[0] = (unsigned)xm * ES;
-    co[1] = (unsigned)Xw * ES;
-    co[2] = (unsigned)xp * ES;
+    co[0] = (unsigned)xm * PE;
+    co[1] = (unsigned)Xw * PE;
+    co[2] = (unsigned)xp * PE;
   };
 
   // ------------------------------------------------------------ halo columns
@@ -471,6 +632,14 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const KArgs<T
       L.hr2[hs][hr] = m.rho[1];
 #pragma unroll
       for (int kk = 0; kk < NSA; ++kk) L.hC[kk][hs][hr] = m.C[kk];
+      if constexpr (DEV) {
+        RF<T> r;
+        T cf[NSA];
+        wref(m, r, cf);
+        L.hrf[hs][hr] = r;
+#pragma unroll
+        for (int kk = 0; kk < NSA; ++kk) L.hCf[kk][hs][hr] = cf[kk];
+      }
     }
   }
 
@@ -539,6 +708,14 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const KArgs<T
       L.r2[sp][cl] = mn.rho[1];
 #pragma unroll
       for (int kk = 0; kk < NSA; ++kk) L.C[kk][sp][cl] = mn.C[kk];
+      if constexpr (DEV) {
+        RF<T> r;
+        T cf[NSA];
+        wref(mn, r, cf);
+        L.rf[sp][cl] = r;
+#pragma unroll
+        for (int kk = 0; kk < NSA; ++kk) L.Cf[kk][sp][cl] = cf[kk];
+      }
       if (lane < 2) {
         const int ce = lane ? SW + 1 : 0;
         const int hr = Rn - (y0 - 1);
@@ -547,6 +724,11 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const KArgs<T
         L.r2[sp][ce] = L.hr2[lane][hr];
 #pragma unroll
         for (int kk = 0; kk < NSA; ++kk) L.C[kk][sp][ce] = L.hC[kk][lane][hr];
+        if constexpr (DEV) {
+          L.rf[sp][ce] = L.hrf[lane][hr];
+#pragma unroll
+          for (int kk = 0; kk < NSA; ++kk) L.Cf[kk][sp][ce] = L.hCf[kk][lane][hr];
+        }
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -826,8 +1008,9 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const KArgs<T
 
       // ------------------------------------------------------ node status
       uint32_t wout = 0;
+      bool dissolved = false;
+      T rdis[2] = {T(0), T(0)};  // density given to a dissolved node
       if (!EXPORT && own) {
-        bool dissolved = false;
         uint32_t tnew = (uint32_t)t;
         bool lnew = false;
         if (t == T_FLUID) {
@@ -883,6 +1066,8 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const KArgs<T
               // slots back (slot opp(a) for direction a: the rest populations
               // are the same in opposite directions).
               const T rb0 = sum0 / T(nf), rb1 = sum1 / T(nf);
+              rdis[0] = rb0;
+              rdis[1] = rb1;
 #pragma unroll
               for (int a = 0; a < 9; ++a) {
                 f[0][a] = T(w9(a)) * rb0;
@@ -926,6 +1111,12 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const KArgs<T
         // status word of the next step: type, liquid marks, stranded flag, and
         // which neighbours are fluid / liquid now (the next pull follows them)
         wout = tnew | (lnew ? TB_LIQ : 0u) | (liq ? TB_LIQP : 0u) | (to_f ? TB_STR : 0u);
+        if constexpr (DEV) {
+          // reference codes of the populations stored now (the node's own
+          // density, or the one a dissolved node is given)
+          const T d0 = dissolved ? rdis[0] : m.rho[0], d1 = dissolved ? rdis[1] : m.rho[1];
+          if (fluid || dissolved) wout |= put_codes(ref_code(d0, k.rb1, SH1, MAX1), ref_code(d1, k.rb2, SH2, MAX2));
+        }
         if (!dissolved) {
 #pragma unroll
           for (int b = 1; b < 9; ++b) wout |= (nt[b] & LF_FLU) << (NBF_SHIFT + b - 1 - 6);
@@ -958,23 +1149,87 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const KArgs<T
         bstore<uint32_t>(wout, wt_, (unsigned)X * 4u, (unsigned)R * upitch * 4u);
         const unsigned long long bf = __ballot(storef);
         const unsigned long long bg = __ballot(storeg);
-        const int half = lane >> 5;
-        const bool gf = ((bf >> (32 * half)) & 0xffffffffull) != 0ull;
-        const bool gg = ((bg >> (32 * half)) & 0xffffffffull) != 0ull;
-        const unsigned xo = (unsigned)X * ES;
+        // a 128-byte line holds the slots of 128 / PE lanes (32 for 16-bit
+        // pairs, 16 for FP32, 8 for FP64); the solute code words, 32 lanes
+        constexpr int G = 128 / PE;
+        constexpr unsigned long long GM = (1ull << G) - 1ull;
+        const int gl = lane & ~(G - 1);
+        const bool gf = ((bf >> gl) & GM) != 0ull;
+        const bool gg = ((bg >> gl) & GM) != 0ull;
+        const bool gw = ((bg >> (lane & 32)) & 0xffffffffull) != 0ull;
+        const unsigned xo = (unsigned)X * PE;
         if (gf) {
           const unsigned vo = xo + (unsigned)R * RSF;
+          if constexpr (DEV) {
+            // deviation from w_a x the reference of the node that pulls the
+            // population next step: the neighbour it heads to if that one is
+            // fluid now, else this node (bounce-back; a dissolved node reads
+            // all its slots back)
+            RF<T> ro;
+            if (dissolved) {
+              ro.r1 = ref_value(ref_code(rdis[0], k.rb1, SH1, MAX1), k.rb1, SH1);
+              ro.r2 = ref_value(ref_code(rdis[1], k.rb2, SH2, MAX2), k.rb2, SH2);
+            } else {
+              ro = L.rf[s0][lane + 1];
+            }
 #pragma unroll
-          for (int s = 0; s < 2; ++s)
+            for (int a = 0; a < 9; ++a) {
+              RF<T> rd = ro;
+              if (a != 0 && !dissolved && is_fluid(nt[a])) rd = L.rf[slot(ey(a))][lane + 1 + ex(a)];
+              bstore2<ST>(dev_out<SM>(__builtin_fmaf(f[0][a], k.sc[0], -(k.wsc[0][wcls(a)] * rd.r1))),
+                          dev_out<SM>(__builtin_fmaf(f[1][a], k.sc[1], -(k.wsc[1][wcls(a)] * rd.r2))), wf_, vo,
+                          (unsigned)a * PS);
+            }
+          } else {
 #pragma unroll
-            for (int a = 0; a < 9; ++a) bstore<T>(f[s][a], wf_, vo, (unsigned)(s * 9 + a) * PS);
+            for (int a = 0; a < 9; ++a) bstore2<ST>(f[0][a], f[1][a], wf_, vo, (unsigned)a * PS);
+          }
         }
         if (NS > 0 && gg) {
           const unsigned vo = xo + (unsigned)R * RSG;
+          if constexpr (DEV) {
+            // deviation from J_a x the reference concentration of the reader:
+            // the liquid neighbour it heads to, else this node
+            T co_[NSA];
 #pragma unroll
-          for (int kk = 0; kk < NS; ++kk)
+            for (int kk = 0; kk < NSA; ++kk) co_[kk] = L.Cf[kk][s0][lane + 1];
 #pragma unroll
-            for (int a = 0; a < 5; ++a) bstore<T>(g[kk][a], wg_, vo, (unsigned)(kk * 5 + a) * PS);
+            for (int a = 0; a < 5; ++a) {
+              const bool nbr = a != 0 && is_liq(nt[a]);
+              uint16_t hv[2 * NSP > 0 ? 2 * NSP : 1];
+#pragma unroll
+              for (int kk = 0; kk < 2 * NSP; ++kk) {
+                if (kk < NS) {
+                  const T cr = nbr ? L.Cf[kk][slot(ey(a))][lane + 1 + ex(a)] : co_[kk];
+                  hv[kk] = dev_out<SM>(__builtin_fmaf(g[kk][a], k.scg[kk], -(k.Jsc[kk][a == 0 ? 0 : 1] * cr)));
+                } else {
+                  hv[kk] = 0;
+                }
+              }
+#pragma unroll
+              for (int j = 0; j < NSP; ++j) bstore2<ST>(hv[2 * j], hv[2 * j + 1], wg_, vo, (unsigned)(j * 5 + a) * PS);
+            }
+            // the node's solute reference codes, for its own pull next step
+            const __amdgpu_buffer_rsrc_t wc_ = rsrc_of(A.c_out, c.cbytes);
+            uint32_t cw0 = 0u, cw1 = 0u;
+#pragma unroll
+            for (int kk = 0; kk < NS; ++kk) {
+              const uint32_t cc = ref_code(m.C[kk], k.rbc[kk], SHC, MAXC) << (8 * (kk & 3));
+              if (kk < 4) cw0 |= cc;
+              else cw1 |= cc;
+            }
+            const unsigned cvo = (unsigned)X * 4u + (unsigned)R * ncw * upitch * 4u;
+            if (gw) {
+              bstore<uint32_t>(cw0, wc_, cvo, 0u);
+              if (NS > 4) bstore<uint32_t>(cw1, wc_, cvo, upitch * 4u);
+            }
+          } else {
+#pragma unroll
+            for (int j = 0; j < NSP; ++j)
+#pragma unroll
+              for (int a = 0; a < 5; ++a)
+                bstore2<ST>(g[2 * j][a], 2 * j + 1 < NS ? g[2 * j + 1][a] : T(0), wg_, vo, (unsigned)(j * 5 + a) * PS);
+          }
         }
       }
     }
@@ -1055,19 +1310,26 @@ constexpr int SEG_ROWS = 16;  // default rows per item (LBRX_SEG_ROWS overrides,
 
 template <typename T> using KFnT = void (*)(const KArgs<T>);
 
-template <typename T, bool EXPORT>
+template <typename T, int SM, bool EXPORT>
 KFnT<T> pick(int ns) {
   switch (ns) {
-    case 0: return k_step<T, 0, EXPORT>;
-    case 1: return k_step<T, 1, EXPORT>;
-    case 2: return k_step<T, 2, EXPORT>;
-    case 3: return k_step<T, 3, EXPORT>;
-    case 4: return k_step<T, 4, EXPORT>;
-    case 5: return k_step<T, 5, EXPORT>;
-    case 6: return k_step<T, 6, EXPORT>;
-    case 7: return k_step<T, 7, EXPORT>;
-    default: return k_step<T, 8, EXPORT>;
+    case 0: return k_step<T, SM, 0, EXPORT>;
+    case 1: return k_step<T, SM, 1, EXPORT>;
+    case 2: return k_step<T, SM, 2, EXPORT>;
+    case 3: return k_step<T, SM, 3, EXPORT>;
+    case 4: return k_step<T, SM, 4, EXPORT>;
+    case 5: return k_step<T, SM, 5, EXPORT>;
+    case 6: return k_step<T, SM, 6, EXPORT>;
+    case 7: return k_step<T, SM, 7, EXPORT>;
+    default: return k_step<T, SM, 8, EXPORT>;
   }
+}
+
+int storage_mode(int precision) {
+  return precision == LBRX_F16DEV ? SM_F16 : precision == LBRX_BF16DEV ? SM_BF16 : SM_PLAIN;
+}
+size_t storage_bytes(int precision) {
+  return precision == LBRX_F64 ? 8 : precision == LBRX_F32 ? 4 : 2;
 }
 
 thread_local std::string g_create_err;
@@ -1084,6 +1346,7 @@ struct lbrx_ctx {
   void* f[2] = {nullptr, nullptr};
   void* g[2] = {nullptr, nullptr};
   uint32_t* t[2] = {nullptr, nullptr};
+  uint32_t* cw[2] = {nullptr, nullptr};  // solute reference codes (16-bit storage)
   double* V = nullptr;
   unsigned long long* rmax = nullptr;
   double* led = nullptr;
@@ -1122,7 +1385,9 @@ std::string validate(const lbrx_params* p) {
   if (p->abi_version != LBRX_ABI_VERSION) return "abi_version mismatch";
   if (p->nx < 1 || p->ny < 1) return "nx and ny must be >= 1";
   if ((long long)p->nx * p->ny > (1ll << 31) - 1) return "lattice too large";
-  if (p->precision != LBRX_F64 && p->precision != LBRX_F32) return "unknown precision";
+  if (p->precision != LBRX_F64 && p->precision != LBRX_F32 && p->precision != LBRX_F16DEV &&
+      p->precision != LBRX_BF16DEV)
+    return "unknown precision";
   for (int s = 0; s < 2; ++s)
     if (!(p->tau[s] > 0.5)) return "tau must exceed 1/2";
   if (p->n_species < 0 || p->n_species > LBRX_MAX_SPECIES) return "n_species out of range";
@@ -1156,9 +1421,10 @@ std::string validate(const lbrx_params* p) {
   {
     // the kernels address each population array with 32-bit byte offsets
     const unsigned long long pitch = ((unsigned long long)p->nx + 63) / 64 * 64;
-    const unsigned long long esz = p->precision == LBRX_F64 ? 8 : 4;
-    const unsigned long long np = 18ull > 5ull * p->n_species ? 18ull : 5ull * p->n_species;
-    if (np * pitch * (unsigned long long)p->ny * esz >= (1ull << 32))
+    const unsigned long long esz = storage_bytes(p->precision);
+    // slots of pairs: 9 flow planes, 5 planes per pair of species
+    const unsigned long long np = 9ull > 5ull * ((p->n_species + 1) / 2) ? 9ull : 5ull * ((p->n_species + 1) / 2);
+    if (np * pitch * (unsigned long long)p->ny * 2ull * esz >= (1ull << 32))
       return "lattice too large: a population array must stay below 4 GiB (use FP32 or fewer species)";
   }
   if (ns > 0 && !p->C0) return "C0 is required when n_species > 0";
@@ -1176,27 +1442,140 @@ std::string validate(const lbrx_params* p) {
   return "";
 }
 
+// Element index of the slot layout: row-interleaved planes of pairs.  Flow:
+// plane a of row y holds (component 1, component 2) of direction a; solute:
+// plane 5j + a holds (species 2j, species 2j + 1) of direction a.
+inline long long fslot(const KConst& c, int y, int a, int x, int s) {
+  return (((long long)y * 9 + a) * c.pitch + x) * 2 + s;
+}
+inline long long gslot(const KConst& c, int y, int k, int a, int x) {
+  const int nsp = (c.ns + 1) / 2;
+  return (((long long)y * 5 * nsp + (k >> 1) * 5 + a) * c.pitch + x) * 2 + (k & 1);
+}
+size_t f_elems(const KConst& c) { return (size_t)18 * c.plane; }
+size_t g_elems(const KConst& c) { return (size_t)10 * ((c.ns + 1) / 2) * c.plane + 2; }
+
 template <typename T>
 void fill_populations(const lbrx_params* p, const KConst& c, const std::vector<uint32_t>& tb,
                       std::vector<T>& f, std::vector<T>& g) {
   const int nx = p->nx, ny = p->ny, ns = p->n_species;
-  const long long plane = c.plane;
-  f.assign((size_t)18 * plane, T(0));
-  g.assign((size_t)5 * ns * plane + 1, T(0));
+  f.assign(f_elems(c), T(0));
+  g.assign(g_elems(c), T(0));
   for (int y = 0; y < ny; ++y)
     for (int x = 0; x < nx; ++x) {
       const long long i = (long long)y * nx + x, d = (long long)y * c.pitch + x;
       if ((tb[d] & TB_T) != T_FLUID) continue;
-      // row-interleaved storage: population q of node (x, y) at (y * NP + q) * pitch + x
-      const long long rf = (long long)y * 18 * c.pitch + x, rg = (long long)y * 5 * ns * c.pitch + x;
       for (int a = 0; a < 9; ++a) {
-        f[rf + (long long)a * c.pitch] = T(w9(a) * p->rho1[i]);
-        f[rf + (long long)(9 + a) * c.pitch] = T(w9(a) * p->rho2[i]);
+        f[fslot(c, y, a, x, 0)] = T(w9(a) * p->rho1[i]);
+        f[fslot(c, y, a, x, 1)] = T(w9(a) * p->rho2[i]);
       }
       if (tb[d] & TB_LIQ)
         for (int k = 0; k < ns; ++k)
-          for (int a = 0; a < 5; ++a)
-            g[rg + (long long)(k * 5 + a) * c.pitch] = T(c.J[k][a] * p->C0[(long long)k * nx * ny + i]);
+          for (int a = 0; a < 5; ++a) g[gslot(c, y, k, a, x)] = T(c.J[k][a] * p->C0[(long long)k * nx * ny + i]);
+    }
+}
+
+// 16-bit storage: the deviation scales are powers of two such that a stored
+// deviation stays far below the FP16 maximum even if every population of a
+// node held six times the largest initial density (or concentration sum);
+// the reference codes cover sixteen binades from an eighth of the smallest
+// initial density (2^-14 of the concentration sum) upward.
+double pow2_scale(double vmax) {
+  if (!(vmax > 0.0)) vmax = 1.0;
+  int e = (int)std::floor(std::log2(65504.0 / (6.0 * vmax)));
+  e = e < -60 ? -60 : (e > 60 ? 60 : e);
+  return std::ldexp(1.0, e);
+}
+uint32_t code_base(double v, int sh) {
+  const float f = (float)(v > 1e-30 ? v : 1e-30);
+  return __builtin_bit_cast(uint32_t, f) >> sh;
+}
+
+void fill_dev_constants(KT<float>& k, const lbrx_params* p, const KConst& c) {
+  const long long N = (long long)p->nx * p->ny;
+  double mx[2] = {0.0, 0.0}, mn[2] = {1e300, 1e300};
+  for (long long i = 0; i < N; ++i) {
+    if (p->node_type[i] != LBRX_FLUID) continue;
+    const double r[2] = {p->rho1[i], p->rho2[i]};
+    for (int s = 0; s < 2; ++s) {
+      mx[s] = std::max(mx[s], r[s]);
+      if (r[s] > 0.0) mn[s] = std::min(mn[s], r[s]);
+    }
+  }
+  double csum = 0.0;
+  for (int q = 0; q < c.ns; ++q) {
+    double m = 0.0;
+    for (long long i = 0; i < N; ++i) m = std::max(m, p->C0[(long long)q * N + i]);
+    csum += m;
+  }
+  if (!(csum > 0.0)) csum = 1.0;
+  const double wv[3] = {4.0 / 9, 1.0 / 9, 1.0 / 36};
+  for (int s = 0; s < 2; ++s) {
+    const double sc = pow2_scale(mx[s]);
+    k.sc[s] = (float)sc;
+    k.isc[s] = (float)(1.0 / sc);
+    for (int q = 0; q < 3; ++q) k.wsc[s][q] = (float)(wv[q] * sc);
+  }
+  for (int q = 0; q < 3; ++q) k.wc[q] = (float)wv[q];
+  k.rb1 = code_base((mn[0] < 1e300 ? mn[0] : 1.0) / 8.0, SH1);
+  k.rb2 = code_base(std::max(mn[1] < 1e300 ? mn[1] : 0.0, 1e-3 * mx[1]) / 8.0, SH2);
+  const double scg = pow2_scale(csum);
+  for (int q = 0; q < LBRX_MAX_SPECIES; ++q) {
+    k.scg[q] = (float)scg;
+    k.iscg[q] = (float)(1.0 / scg);
+    const double J0 = q < c.ns ? c.J[q][0] : 0.0, J1 = q < c.ns ? c.J[q][1] : 0.0;
+    k.Jc[q][0] = (float)J0;
+    k.Jc[q][1] = (float)J1;
+    k.Jsc[q][0] = (float)(J0 * scg);
+    k.Jsc[q][1] = (float)(J1 * scg);
+    k.rbc[q] = code_base(csum * std::ldexp(1.0, -14), SHC);
+  }
+}
+
+uint16_t dev_store_host(float v, int sm) {
+  if (sm == SM_F16) return __builtin_bit_cast(uint16_t, (_Float16)v);
+  // BF16, round to nearest even (finite values)
+  uint32_t u = __builtin_bit_cast(uint32_t, v);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// Initial state in 16-bit form: the rest equilibria of Eq. 8 and 21 as
+// deviations from the references coded in the status and solute words (every
+// node reads its own slots at step 0).
+void fill_dev_populations(const lbrx_params* p, const KConst& c, const KT<float>& k, int sm,
+                          std::vector<uint32_t>& tb, std::vector<uint16_t>& f, std::vector<uint16_t>& g,
+                          std::vector<uint32_t>& cw) {
+  const int nx = p->nx, ny = p->ny, ns = p->n_species;
+  const long long plane = c.plane;
+  f.assign(f_elems(c), 0);
+  g.assign(g_elems(c), 0);
+  cw.assign((size_t)(c.ncw > 0 ? c.ncw : 0) * plane, 0u);
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      const long long i = (long long)y * nx + x, d = (long long)y * c.pitch + x;
+      if ((tb[d] & TB_T) != T_FLUID) continue;
+      const float r[2] = {(float)p->rho1[i], (float)p->rho2[i]};
+      const uint32_t c1 = ref_code(r[0], k.rb1, SH1, MAX1), c2 = ref_code(r[1], k.rb2, SH2, MAX2);
+      tb[d] |= put_codes(c1, c2);
+      const float ref[2] = {ref_value(c1, k.rb1, SH1), ref_value(c2, k.rb2, SH2)};
+      for (int s = 0; s < 2; ++s)
+        for (int a = 0; a < 9; ++a) {
+          const float f0 = (float)(w9(a) * (s == 0 ? p->rho1[i] : p->rho2[i]));
+          f[fslot(c, y, a, x, s)] = dev_store_host(std::fma(f0, k.sc[s], -(k.wsc[s][wcls(a)] * ref[s])), sm);
+        }
+      if ((tb[d] & TB_LIQ) && ns > 0) {
+        for (int q = 0; q < ns; ++q) {
+          const float C = (float)p->C0[(long long)q * nx * ny + i];
+          const uint32_t cc = ref_code(C, k.rbc[q], SHC, MAXC);
+          cw[(size_t)((long long)y * c.ncw + (q >> 2)) * c.pitch + x] |= cc << (8 * (q & 3));
+          const float cr = ref_value(cc, k.rbc[q], SHC);
+          for (int a = 0; a < 5; ++a) {
+            const float g0 = (float)(c.J[q][a] * p->C0[(long long)q * nx * ny + i]);
+            g[gslot(c, y, q, a, x)] = dev_store_host(std::fma(g0, k.scg[q], -(k.Jsc[q][a == 0 ? 0 : 1] * cr)), sm);
+          }
+        }
+      }
     }
 }
 
@@ -1210,6 +1589,8 @@ void fill_args(lbrx_ctx* x, KArgs<T>& A, const KT<T>& kt) {
   A.f_out = x->f[1 - x->cur];
   A.g_out = x->g[1 - x->cur];
   A.t_out = x->t[1 - x->cur];
+  A.c_in = x->cw[x->cur];
+  A.c_out = x->cw[1 - x->cur];
   A.V = x->V;
   A.rmax = x->rmax;
   const int s = (int)(x->steps % 3);
@@ -1325,7 +1706,7 @@ lbrx_status lbrx_create(const lbrx_params* p, void* hip_stream, lbrx_ctx** out) 
   c.plane = (long long)c.pitch * p->ny;
   c.ns = p->n_species;
   x->precision = p->precision;
-  x->esz = p->precision == LBRX_F64 ? 8 : 4;
+  x->esz = storage_bytes(p->precision);
   c.seg_rows = SEG_ROWS;
   if (const char* e = getenv("LBRX_SEG_ROWS")) {
     const int v = atoi(e);
@@ -1335,9 +1716,12 @@ lbrx_status lbrx_create(const lbrx_params* p, void* hip_stream, lbrx_ctx** out) 
   c.nitems = c.strips * ((p->ny + c.seg_rows - 1) / c.seg_rows);
   c.nblocks = (c.nitems + WPB - 1) / WPB;
   // byte sizes of the population and status arrays (below 4 GiB, checked in validate)
-  c.fbytes = (unsigned)(18ull * (unsigned long long)c.plane * x->esz);
-  c.gbytes = (unsigned)((5ull * c.ns * (unsigned long long)c.plane + 1) * x->esz);
+  c.fbytes = (unsigned)(f_elems(c) * x->esz);
+  c.gbytes = (unsigned)(g_elems(c) * x->esz);
   c.tbytes = (unsigned)((unsigned long long)c.plane * 4ull);
+  const int sm = storage_mode(p->precision);
+  c.ncw = (sm != SM_PLAIN && c.ns > 0) ? (c.ns + 3) / 4 : 0;
+  c.cbytes = (unsigned)((unsigned long long)(c.ncw > 0 ? c.ncw : 1) * c.plane * 4ull);
   for (int s = 0; s < 2; ++s) {
     c.tau[s] = p->tau[s];
     c.om[s] = 1.0 / p->tau[s];
@@ -1394,10 +1778,13 @@ lbrx_status lbrx_create(const lbrx_params* p, void* hip_stream, lbrx_ctx** out) 
   }
   fill_kt(x->kd, p, c, D);
   fill_kt(x->kf, p, c, D);
-  x->step64 = pick<double, false>(c.ns);
-  x->export64 = pick<double, true>(c.ns);
-  x->step32 = pick<float, false>(c.ns);
-  x->export32 = pick<float, true>(c.ns);
+  if (sm != SM_PLAIN) fill_dev_constants(x->kf, p, c);
+  x->step64 = pick<double, SM_PLAIN, false>(c.ns);
+  x->export64 = pick<double, SM_PLAIN, true>(c.ns);
+  x->step32 = sm == SM_F16 ? pick<float, SM_F16, false>(c.ns)
+             : sm == SM_BF16 ? pick<float, SM_BF16, false>(c.ns) : pick<float, SM_PLAIN, false>(c.ns);
+  x->export32 = sm == SM_F16 ? pick<float, SM_F16, true>(c.ns)
+               : sm == SM_BF16 ? pick<float, SM_BF16, true>(c.ns) : pick<float, SM_PLAIN, true>(c.ns);
 
   auto fail = [&](lbrx_status s, const std::string& m) {
     g_create_err = m;
@@ -1413,10 +1800,10 @@ lbrx_status lbrx_create(const lbrx_params* p, void* hip_stream, lbrx_ctx** out) 
     x->own_stream = true;
   }
   const size_t plane = (size_t)c.plane;
-  const size_t fbytes = 18 * plane * x->esz, gbytes = (5 * (size_t)c.ns * plane + 1) * x->esz;
+  const size_t fbytes = f_elems(c) * x->esz, gbytes = g_elems(c) * x->esz;
   for (int i = 0; i < 2; ++i) {
     if (hipMalloc(&x->f[i], fbytes) != hipSuccess || hipMalloc(&x->g[i], gbytes) != hipSuccess ||
-        hipMalloc((void**)&x->t[i], plane * 4) != hipSuccess)
+        hipMalloc((void**)&x->t[i], plane * 4) != hipSuccess || hipMalloc((void**)&x->cw[i], c.cbytes) != hipSuccess)
       return fail(LBRX_E_NOMEM, "device allocation of the populations failed");
   }
   if (hipMalloc((void**)&x->V, plane * 8) != hipSuccess || hipMalloc((void**)&x->rmax, RM_WORDS * 8) != hipSuccess ||
@@ -1449,11 +1836,18 @@ lbrx_status lbrx_create(const lbrx_params* p, void* hip_stream, lbrx_ctx** out) 
     fill_populations<double>(p, c, tb, f, g);
     e = hipMemcpy(x->f[0], f.data(), fbytes, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(x->g[0], g.data(), gbytes, hipMemcpyHostToDevice);
-  } else {
+  } else if (sm == SM_PLAIN) {
     std::vector<float> f, g;
     fill_populations<float>(p, c, tb, f, g);
     e = hipMemcpy(x->f[0], f.data(), fbytes, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(x->g[0], g.data(), gbytes, hipMemcpyHostToDevice);
+  } else {
+    std::vector<uint16_t> f, g;
+    std::vector<uint32_t> cw;
+    fill_dev_populations(p, c, x->kf, sm, tb, f, g, cw);
+    e = hipMemcpy(x->f[0], f.data(), fbytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(x->g[0], g.data(), gbytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess && !cw.empty()) e = hipMemcpy(x->cw[0], cw.data(), cw.size() * 4, hipMemcpyHostToDevice);
   }
   // the second buffers start as copies so that never-written slots hold defined values
   if (e == hipSuccess) e = hipMemcpy(x->f[1], x->f[0], fbytes, hipMemcpyDeviceToDevice);
@@ -1590,6 +1984,7 @@ lbrx_status lbrx_destroy(lbrx_ctx* x) {
     if (x->f[i]) (void)hipFree(x->f[i]);
     if (x->g[i]) (void)hipFree(x->g[i]);
     if (x->t[i]) (void)hipFree(x->t[i]);
+    if (x->cw[i]) (void)hipFree(x->cw[i]);
   }
   if (x->V) (void)hipFree(x->V);
   if (x->rmax) (void)hipFree(x->rmax);

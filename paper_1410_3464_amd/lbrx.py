@@ -17,8 +17,8 @@ LIB_PATH = os.path.join(HERE, "liblbrx.so")
 ABI_VERSION = 1
 MAXS = 8
 MAXR = 8
-F64, F32 = 0, 1
-_PREC = {"f64": F64, "f32": F32}
+F64, F32, F16DEV, BF16DEV = 0, 1, 2, 3
+_PREC = {"f64": F64, "f32": F32, "f16dev": F16DEV, "bf16dev": BF16DEV}
 _HOM = {"first_order": 0, "r1_gas": 1, "bimolecular": 2}
 _HET = {"consumes": 0, "grows": 1, "mineral": 2}
 STATUS = {0: "LBRX_OK", 1: "LBRX_E_INVAL", 2: "LBRX_E_NOMEM", 3: "LBRX_E_DEVICE",
