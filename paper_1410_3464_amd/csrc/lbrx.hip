@@ -168,11 +168,14 @@ template <typename T> struct KArgs {
 
 enum { ERR_DENSITY = 1u, ERR_EOS = 2u };
 
+// Coordinate X inside [0, n) (periodic) or "outside" (false).  The callers'
+// coordinates lie at most 66 nodes outside, so a few additions or
+// subtractions wrap them (one unless n is tiny); no integer division.
 __device__ inline bool wrap(int& X, int n, int per) {
   if (X >= 0 && X < n) return true;
   if (!per) return false;
-  X %= n;
-  if (X < 0) X += n;
+  while (X < 0) X += n;
+  while (X >= n) X -= n;
   return true;
 }
 
@@ -670,11 +673,16 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const KArgs<T
   // The first two iterations (R = y0 - 2, y0 - 1) only fill the ring.
   T fc[2][9], gc[NSA][5];
   Mom<T, NS> mc;
-  uint32_t w_cur = 0, w_next = word_at(X, y0 - 1);
+  // status word of this lane's column in row Y (the column is wrapped once)
+  auto word_row = [&](int Y) -> uint32_t {
+    if (colin && wrap(Y, ny, c.per_y)) return bload<uint32_t>(rt, (unsigned)Xw * 4u, (unsigned)Y * upitch * 4u);
+    return TB_WALL;
+  };
+  uint32_t w_cur = 0, w_next = word_row(y0 - 1);
   int sm = 1, s0 = 2, sp = 0;
   for (int R = y0 - 2; R < y1; ++R) {
     const int Rn = R + 1;
-    const uint32_t w_nn = word_at(X, R + 2);  // next iteration's row, loaded ahead
+    const uint32_t w_nn = word_row(R + 2);  // next iteration's row, loaded ahead
     T fn[2][9], gn[NSA][5];
     Mom<T, NS> mn;
     {
@@ -887,6 +895,7 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const KArgs<T
             for (int a = 1; a < 9; ++a) {
               if (!(nt[a] & TB_WALL) && (nt[a] & TB_STR)) {
                 int mm = 0;
+#pragma unroll 1
                 for (int b = 1; b < 9; ++b) mm += is_fluid(far_flags(ex(a) + ex(b), ey(a) + ey(b))) ? 1 : 0;
                 const int sl = slot(ey(a)), lx = lane + 1 + ex(a);
                 don[0] += L.r1[sl][lx] / T(mm);
@@ -943,6 +952,7 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const KArgs<T
               for (int a = 1; a < 5; ++a) {
                 if (!(nt[a] & TB_WALL) && (nt[a] & TB_LIQP) && !(nt[a] & LF_LIQN)) {
                   int mm = 0;
+#pragma unroll 1
                   for (int b = 1; b < 5; ++b) mm += is_liq(far_flags(ex(a) + ex(b), ey(a) + ey(b))) ? 1 : 0;
                   const int sl = slot(ey(a)), lx = lane + 1 + ex(a);
 #pragma unroll
@@ -1296,13 +1306,22 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const KArgs<T
 }
 
 // ---------------------------------------------------------------- ledger sum
-// Fixed-order sum of the per-item balance records (one block, one field per thread).
-__global__ void k_ledger_sum(const double* led, int nitems, double* out) {
-  const int f = threadIdx.x;
-  if (f >= NLED) return;
+// Fixed-order sum of the per-item balance records: one workgroup per ledger
+// field; thread t adds items t, t + 256, ... in order, then a fixed tree adds
+// the 256 partial sums (the same result on every call).
+constexpr int LSUM_THREADS = 256;
+__global__ __launch_bounds__(LSUM_THREADS) void k_ledger_sum(const double* led, int nitems, double* out) {
+  __shared__ double part[LSUM_THREADS];
+  const int f = blockIdx.x, t = threadIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nitems; ++b) s += led[(long long)b * NLED + f];
-  out[f] = s;
+  for (int b = t; b < nitems; b += LSUM_THREADS) s += led[(long long)b * NLED + f];
+  part[t] = s;
+  __syncthreads();
+  for (int h = LSUM_THREADS / 2; h > 0; h >>= 1) {
+    if (t < h) part[t] += part[t + h];
+    __syncthreads();
+  }
+  if (t == 0) out[f] = part[0];
 }
 
 // ---------------------------------------------------------------- host side
@@ -1925,7 +1944,7 @@ lbrx_status lbrx_fields(lbrx_ctx* x, lbrx_fields_out* o) {
     hipLaunchKernelGGL(x->export32, grid, block, 0, x->stream, A);
   }
   HIPCHK(x, hipGetLastError());
-  hipLaunchKernelGGL(k_ledger_sum, dim3(1), dim3(64), 0, x->stream, x->led, c.nitems, x->ledsum);
+  hipLaunchKernelGGL(k_ledger_sum, dim3(NLED), dim3(LSUM_THREADS), 0, x->stream, x->led, c.nitems, x->ledsum);
   HIPCHK(x, hipGetLastError());
   HIPCHK(x, hipStreamSynchronize(x->stream));
   const size_t sp = (size_t)c.pitch * 8, dp = (size_t)c.nx * 8;
