@@ -31,11 +31,12 @@
 extern "C" {
 #endif
 
-#define LBRX_ABI_VERSION 1u
+#define LBRX_ABI_VERSION 2u
 #define LBRX_MAX_SPECIES 8
 #define LBRX_MAX_RXN 8
 
 typedef struct lbrx_ctx lbrx_ctx;
+typedef struct lbrx_batch lbrx_batch;
 
 typedef enum {
   LBRX_OK = 0,
@@ -124,6 +125,10 @@ typedef struct {
   const double* rho1;       /* > 0 at fluid nodes */
   const double* rho2;       /* >= 0 at fluid nodes */
   const double* C0;         /* used at nodes that start liquid; may be NULL if n_species == 0 */
+  /* work decomposition: rows per work item of the step kernel (each item is
+     64 columns by seg_rows rows, one wavefront), 1..30; 0 picks 16.  It
+     changes the speed, not the result. */
+  int32_t seg_rows;
 } lbrx_params;
 
 /* Cumulative balances, FP64.  With M_s the total of component s and S_k the
@@ -197,6 +202,32 @@ const char* lbrx_last_error(const lbrx_ctx* ctx);
 
 /* Static name of a status code. */
 const char* lbrx_status_string(lbrx_status s);
+
+/* ---- batches: several simulations advanced by one launch per step -------
+ * Not a method of the paper: a way to run many independent (small) problems,
+ * each still the coupled step of Sec. 4.7, with one kernel launch per step
+ * for all of them.  Results are identical to stepping each context alone.
+ *
+ * Creates a batch of n >= 1 distinct contexts that share device, stream,
+ * precision and species count (LBRX_E_INVAL otherwise; also for more than
+ * 4095 contexts or a context of more than 131072 work items).  The batch
+ * keeps pointers to the contexts, which must outlive it; it copies nothing
+ * of their state.  A context may still be stepped, read and synced on its
+ * own; a batch notices and rebuilds its tables. */
+lbrx_status lbrx_batch_create(lbrx_ctx* const* ctxs, int n, lbrx_batch** out);
+
+/* Enqueues n_steps >= 0 steps of every context of the batch on their stream
+ * (one launch per step; runs of 30 steps replay a captured HIP graph) and
+ * returns without waiting.  Numerical failures are reported per context by
+ * lbrx_sync / lbrx_fields. */
+lbrx_status lbrx_batch_step(lbrx_batch* batch, int64_t n_steps);
+
+/* Message for the last failure of this batch. */
+const char* lbrx_batch_last_error(const lbrx_batch* batch);
+
+/* Waits for the batch's stream and releases the batch (not the contexts).
+ * NULL is a no-op. */
+lbrx_status lbrx_batch_destroy(lbrx_batch* batch);
 
 #ifdef __cplusplus
 }

@@ -147,24 +147,40 @@ template <typename T> struct KT {
   uint32_t rb1, rb2, rbc[LBRX_MAX_SPECIES];
 };
 
+// Everything a launch needs about one simulation, kept in device memory for
+// the simulation's lifetime: the buffer pair of each array (which one is read
+// follows from the step count), constants, and state.
 template <typename T> struct KArgs {
   KConst c;
   KT<T> k;
-  const void* f_in;
-  void* f_out;
-  const void* g_in;
-  void* g_out;
-  const uint32_t* t_in;
-  uint32_t* t_out;
-  const uint32_t* c_in;  // solute reference codes (16-bit storage)
-  uint32_t* c_out;
+  void* f[2];
+  void* g[2];
+  uint32_t* t[2];
+  uint32_t* cw[2];           // solute reference codes (16-bit storage)
   double* V;
   unsigned long long* rmax;  // 3 rotating slots
-  int slot_prev, slot_cur, slot_next;
   double* led;               // [nitems][NLED]
   unsigned int* err;         // [0] flags, [1] first failing node (min index)
   double *o_r1, *o_r2, *o_ux, *o_uy, *o_C;  // export outputs (plane-sized)
 };
+
+// constant address space: data no store of a running kernel can change
+#define KAS __attribute__((address_space(4)))
+
+// The kernel arguments of one launch: one simulation (ninst == 0), or a batch
+// whose workgroups each look up their simulation, item block and step phase
+// in a table.  The phase of a simulation is its step count modulo 6: bit 0
+// picks the buffer that is read, the count modulo 3 the rho_max slot.
+struct LaunchArgs {
+  const void* single;       // KArgs of the simulation (ninst == 0)
+  const void* const* inst;  // batch: KArgs of every simulation
+  const uint32_t* table;    // batch: per workgroup, simulation << 20 | base phase << 17 | block
+  int ninst;
+  int phase0;  // single: step count mod 6
+  int launch;  // batch: launches since the table was built, mod 6
+};
+constexpr int TAB_INST_SHIFT = 20, TAB_PHASE_SHIFT = 17;
+constexpr uint32_t TAB_BLOCK_MASK = (1u << TAB_PHASE_SHIFT) - 1u;
 
 enum { ERR_DENSITY = 1u, ERR_EOS = 2u };
 
@@ -234,7 +250,7 @@ template <typename T> __device__ inline T wave_max_t(T v) {
 }
 
 // Carnahan-Starling pressure (Eq. 12), same operation order as the text.
-template <typename T> __device__ inline T p_cs(const KT<T>& k, T rho) {
+template <typename T, typename K> __device__ inline T p_cs(const K& k, T rho) {
   const T e = T(0.25) * k.b * rho;
   const T om = T(1) - e;
   const T num = T(1) + e + e * e - e * e * e;
@@ -394,31 +410,56 @@ template <typename T, int NS> struct Mom {
 };
 
 template <typename T, int SM, int NS, bool EXPORT>
-__global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const KArgs<T> A_arg) {
-  // The arguments are read where the launch put them (the kernarg segment, a
-  // constant address space): the helpers below refer to them, and a reference
-  // to the by-value parameter itself would make the compiler copy the whole
-  // block to private memory first.
-  (void)A_arg;
-  const KArgs<T>& A = *(const KArgs<T>*)__builtin_amdgcn_kernarg_segment_ptr();
+__global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchArgs LA_arg) {
+  // The launch arguments are read where the launch put them (the kernarg
+  // segment): a reference to the by-value parameter itself would make the
+  // compiler copy it to private memory first.
+  (void)LA_arg;
+  const LaunchArgs& LA = *(const LaunchArgs*)__builtin_amdgcn_kernarg_segment_ptr();
+
+  // XCD-aware order: consecutive workgroups are dealt round-robin to the 8
+  // XCDs; each XCD gets a contiguous band of items (of a batch's table), so
+  // that the halo rows two vertically neighbouring items share sit in the
+  // same L2.
+  const int nb = gridDim.x;
+  const int bid = blockIdx.x;
+  const int xcd = bid & 7, loc = bid >> 3;
+  const int gblk = xcd * (nb >> 3) + min(xcd, nb & 7) + loc;
+  // the simulation, block and phase are the same for the whole workgroup:
+  // kept in scalar registers (readfirstlane), so that its KArgs are read with
+  // scalar loads
+  const void* Ap;
+  int phase, blk;
+  if (LA.ninst == 0) {
+    Ap = LA.single;
+    phase = LA.phase0;
+    blk = gblk;
+  } else {
+    const uint32_t e = __builtin_amdgcn_readfirstlane(LA.table[gblk]);
+    const unsigned long long pa = (unsigned long long)LA.inst[e >> TAB_INST_SHIFT];
+    Ap = (const void*)(((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(pa >> 32)) << 32) |
+                       (unsigned)__builtin_amdgcn_readfirstlane((unsigned)pa));
+    phase = ((int)((e >> TAB_PHASE_SHIFT) & 7u) + LA.launch) % 6;
+    blk = (int)(e & TAB_BLOCK_MASK);
+  }
+  // The simulation's KArgs never change while a kernel runs: reading them
+  // through the constant address space lets the compiler keep them in scalar
+  // registers and scalar loads (through a plain pointer it would reload them
+  // with vector loads after every store).
+  const KAS KArgs<T>& A = *(const KAS KArgs<T>*)Ap;
+  const int cur = phase & 1;
+  const int slot_cur = phase % 3, slot_prev = (slot_cur + 2) % 3, slot_next = (slot_cur + 1) % 3;
   constexpr int NSA = NS > 0 ? NS : 1;
   using ST = typename StoreT<T, SM>::type;  // stored population type
   constexpr unsigned ES = sizeof(ST);
   constexpr bool DEV = SM != SM_PLAIN;
   static_assert(!DEV || std::is_same<T, float>::value, "16-bit storage computes in FP32");
-  const KConst& c = A.c;
-  const KT<T>& k = A.k;
+  const KAS KConst& c = A.c;
+  const KAS KT<T>& k = A.k;
   __shared__ WaveLds<T, NS, SM> s_all[WPB];
   WaveLds<T, NS, SM>& L = s_all[threadIdx.y];
   const int lane = threadIdx.x;
 
-  // XCD-aware order: consecutive workgroups are dealt round-robin to the 8
-  // XCDs; each XCD gets a contiguous band of items, so that the halo rows two
-  // vertically neighbouring items share sit in the same L2.
-  const int nb = gridDim.x;
-  const int bid = blockIdx.x;
-  const int xcd = bid & 7, loc = bid >> 3;
-  const int blk = xcd * (nb >> 3) + min(xcd, nb & 7) + loc;
   const int item = blk * WPB + (int)threadIdx.y;
   if (item >= c.nitems) return;  // whole wavefront
   const int sx = item % c.strips, sy = item / c.strips;
@@ -433,10 +474,10 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const KArgs<T
   const unsigned RSF = 9u * PS;        // bytes per lattice row, flow: 9 directions x (component 1, 2)
   const unsigned RSG = 5u * NSP * PS;  // bytes per lattice row, solute: species pairs x 5 directions
 
-  const __amdgpu_buffer_rsrc_t rf = rsrc_of(A.f_in, c.fbytes);
-  const __amdgpu_buffer_rsrc_t rg = rsrc_of(A.g_in, c.gbytes);
-  const __amdgpu_buffer_rsrc_t rt = rsrc_of(A.t_in, c.tbytes);
-  const __amdgpu_buffer_rsrc_t rcw = rsrc_of(A.c_in, c.cbytes);
+  const __amdgpu_buffer_rsrc_t rf = rsrc_of(A.f[cur], c.fbytes);
+  const __amdgpu_buffer_rsrc_t rg = rsrc_of(A.g[cur], c.gbytes);
+  const __amdgpu_buffer_rsrc_t rt = rsrc_of(A.t[cur], c.tbytes);
+  const __amdgpu_buffer_rsrc_t rcw = rsrc_of(A.cw[cur], c.cbytes);
   const unsigned ncw = (unsigned)c.ncw;
 
   if (!EXPORT && lane < NRARE_SLOTS) L.rare[lane] = 0.0;
@@ -664,7 +705,7 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const KArgs<T
   double rprev = 0.0;
 #pragma unroll
   for (int xc = 0; xc < 8; ++xc)
-    rprev = fmax(rprev, __longlong_as_double((long long)A.rmax[A.slot_prev * RM_SLOT + xc * RM_STRIDE]));
+    rprev = fmax(rprev, __longlong_as_double((long long)A.rmax[slot_prev * RM_SLOT + xc * RM_STRIDE]));
   const double thr = c.lfrac * rprev;
 
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -1153,9 +1194,9 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const KArgs<T
         // lanes when any of them holds valid populations, so that lines are
         // written whole; a lane without valid populations writes values nobody
         // reads (its slots are not pulled from next step).
-        const __amdgpu_buffer_rsrc_t wf_ = rsrc_of(A.f_out, c.fbytes);
-        const __amdgpu_buffer_rsrc_t wg_ = rsrc_of(A.g_out, c.gbytes);
-        const __amdgpu_buffer_rsrc_t wt_ = rsrc_of(A.t_out, c.tbytes);
+        const __amdgpu_buffer_rsrc_t wf_ = rsrc_of(A.f[1 - cur], c.fbytes);
+        const __amdgpu_buffer_rsrc_t wg_ = rsrc_of(A.g[1 - cur], c.gbytes);
+        const __amdgpu_buffer_rsrc_t wt_ = rsrc_of(A.t[1 - cur], c.tbytes);
         bstore<uint32_t>(wout, wt_, (unsigned)X * 4u, (unsigned)R * upitch * 4u);
         const unsigned long long bf = __ballot(storef);
         const unsigned long long bg = __ballot(storeg);
@@ -1220,7 +1261,7 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const KArgs<T
               for (int j = 0; j < NSP; ++j) bstore2<ST>(hv[2 * j], hv[2 * j + 1], wg_, vo, (unsigned)(j * 5 + a) * PS);
             }
             // the node's solute reference codes, for its own pull next step
-            const __amdgpu_buffer_rsrc_t wc_ = rsrc_of(A.c_out, c.cbytes);
+            const __amdgpu_buffer_rsrc_t wc_ = rsrc_of(A.cw[1 - cur], c.cbytes);
             uint32_t cw0 = 0u, cw1 = 0u;
 #pragma unroll
             for (int kk = 0; kk < NS; ++kk) {
@@ -1281,14 +1322,14 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const KArgs<T
   double* Lg = A.led + (size_t)item * NLED;
   if (lane == 0) {
     const double md = (double)wm;
-    unsigned long long* part = &A.rmax[A.slot_cur * RM_SLOT + xcd * RM_STRIDE];
+    unsigned long long* part = &A.rmax[slot_cur * RM_SLOT + xcd * RM_STRIDE];
     const unsigned long long mb = (unsigned long long)__double_as_longlong(md);
     // the partial only grows during a step, so a value already at least as
     // large makes this wavefront's atomic unnecessary
     const unsigned long long seen = __hip_atomic_load(part, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (md > 0.0 && mb > seen) atomicMax(part, mb);
     if (item == 0)
-      for (int xc = 0; xc < 8; ++xc) A.rmax[A.slot_next * RM_SLOT + xc * RM_STRIDE] = 0ull;
+      for (int xc = 0; xc < 8; ++xc) A.rmax[slot_next * RM_SLOT + xc * RM_STRIDE] = 0ull;
     if (v0 != T(0)) Lg[L_MSRC] += (double)v0;
     if (v1 != T(0)) Lg[L_MSRC + 1] += (double)v1;
     if (vd != 0.0) Lg[L_VDV] += vd;
@@ -1327,7 +1368,7 @@ __global__ __launch_bounds__(LSUM_THREADS) void k_ledger_sum(const double* led, 
 // ---------------------------------------------------------------- host side
 constexpr int SEG_ROWS = 16;  // default rows per item (LBRX_SEG_ROWS overrides, 1..HMAX)
 
-template <typename T> using KFnT = void (*)(const KArgs<T>);
+template <typename T> using KFnT = void (*)(const LaunchArgs);
 
 template <typename T, int SM, bool EXPORT>
 KFnT<T> pick(int ns) {
@@ -1372,6 +1413,7 @@ struct lbrx_ctx {
   double* ledsum = nullptr;
   unsigned int* err = nullptr;
   double* out = nullptr;  // export scratch: (4 + ns) planes
+  void* dargs = nullptr;  // this simulation's KArgs in device memory
   int cur = 0;
   int64_t steps = 0;
   bool failed = false;
@@ -1403,6 +1445,7 @@ std::string validate(const lbrx_params* p) {
   if (!p) return "params is NULL";
   if (p->abi_version != LBRX_ABI_VERSION) return "abi_version mismatch";
   if (p->nx < 1 || p->ny < 1) return "nx and ny must be >= 1";
+  if (p->seg_rows < 0 || p->seg_rows > HMAX) return "seg_rows must lie in 0..30";
   if ((long long)p->nx * p->ny > (1ll << 31) - 1) return "lattice too large";
   if (p->precision != LBRX_F64 && p->precision != LBRX_F32 && p->precision != LBRX_F16DEV &&
       p->precision != LBRX_BF16DEV)
@@ -1599,41 +1642,58 @@ void fill_dev_populations(const lbrx_params* p, const KConst& c, const KT<float>
 }
 
 template <typename T>
-void fill_args(lbrx_ctx* x, KArgs<T>& A, const KT<T>& kt) {
+void make_args(const lbrx_ctx* x, KArgs<T>& A, const KT<T>& kt) {
   A.c = x->c;
   A.k = kt;
-  A.f_in = x->f[x->cur];
-  A.g_in = x->g[x->cur];
-  A.t_in = x->t[x->cur];
-  A.f_out = x->f[1 - x->cur];
-  A.g_out = x->g[1 - x->cur];
-  A.t_out = x->t[1 - x->cur];
-  A.c_in = x->cw[x->cur];
-  A.c_out = x->cw[1 - x->cur];
+  for (int i = 0; i < 2; ++i) {
+    A.f[i] = x->f[i];
+    A.g[i] = x->g[i];
+    A.t[i] = x->t[i];
+    A.cw[i] = x->cw[i];
+  }
   A.V = x->V;
   A.rmax = x->rmax;
-  const int s = (int)(x->steps % 3);
-  A.slot_prev = (s + 2) % 3;
-  A.slot_cur = s;
-  A.slot_next = (s + 1) % 3;
   A.led = x->led;
   A.err = x->err;
+  const size_t plane = (size_t)x->c.plane;
+  A.o_r1 = x->out;
+  A.o_r2 = x->out ? x->out + plane : nullptr;
+  A.o_ux = x->out ? x->out + 2 * plane : nullptr;
+  A.o_uy = x->out ? x->out + 3 * plane : nullptr;
+  A.o_C = x->out ? x->out + 4 * plane : nullptr;
+}
+
+// (re)writes the simulation's device-resident KArgs (synchronous copy)
+hipError_t upload_args(lbrx_ctx* x) {
+  if (x->precision == LBRX_F64) {
+    KArgs<double> A{};
+    make_args(x, A, x->kd);
+    return hipMemcpy(x->dargs, &A, sizeof A, hipMemcpyHostToDevice);
+  }
+  KArgs<float> A{};
+  make_args(x, A, x->kf);
+  return hipMemcpy(x->dargs, &A, sizeof A, hipMemcpyHostToDevice);
+}
+
+size_t args_bytes(int precision) { return precision == LBRX_F64 ? sizeof(KArgs<double>) : sizeof(KArgs<float>); }
+
+void launch_one(lbrx_ctx* x, bool exporting) {
+  LaunchArgs L{};
+  L.single = x->dargs;
+  L.ninst = 0;
+  L.phase0 = (int)(x->steps % 6);
+  const dim3 grid(x->c.nblocks), block(64, WPB);
+  if (x->precision == LBRX_F64)
+    hipLaunchKernelGGL(exporting ? x->export64 : x->step64, grid, block, 0, x->stream, L);
+  else
+    hipLaunchKernelGGL(exporting ? x->export32 : x->step32, grid, block, 0, x->stream, L);
 }
 
 lbrx_status launch_step(lbrx_ctx* x) {
-  const dim3 grid(x->c.nblocks), block(64, WPB);
-  if (x->precision == LBRX_F64) {
-    KArgs<double> A{};
-    fill_args(x, A, x->kd);
-    hipLaunchKernelGGL(x->step64, grid, block, 0, x->stream, A);
-  } else {
-    KArgs<float> A{};
-    fill_args(x, A, x->kf);
-    hipLaunchKernelGGL(x->step32, grid, block, 0, x->stream, A);
-  }
+  launch_one(x, false);
   HIPCHK(x, hipGetLastError());
-  x->cur = 1 - x->cur;
   x->steps += 1;
+  x->cur = (int)(x->steps & 1);
   return LBRX_OK;
 }
 
@@ -1726,7 +1786,7 @@ lbrx_status lbrx_create(const lbrx_params* p, void* hip_stream, lbrx_ctx** out) 
   c.ns = p->n_species;
   x->precision = p->precision;
   x->esz = storage_bytes(p->precision);
-  c.seg_rows = SEG_ROWS;
+  c.seg_rows = p->seg_rows > 0 ? p->seg_rows : SEG_ROWS;
   if (const char* e = getenv("LBRX_SEG_ROWS")) {
     const int v = atoi(e);
     if (v >= 1 && v <= HMAX) c.seg_rows = v;
@@ -1880,6 +1940,8 @@ lbrx_status lbrx_create(const lbrx_params* p, void* hip_stream, lbrx_ctx** out) 
   unsigned int er[2] = {0u, 0xffffffffu};
   if (e == hipSuccess) e = hipMemcpy(x->err, er, sizeof er, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(x->led, 0, (size_t)c.nitems * NLED * 8);
+  if (e == hipSuccess) e = hipMalloc(&x->dargs, args_bytes(x->precision));
+  if (e == hipSuccess) e = upload_args(x);
   if (e != hipSuccess) return fail(LBRX_E_DEVICE, std::string("initial copy failed: ") + hipGetErrorString(e));
   *out = x;
   return LBRX_OK;
@@ -1921,28 +1983,12 @@ lbrx_status lbrx_fields(lbrx_ctx* x, lbrx_fields_out* o) {
   if (st != LBRX_OK) return st;
   const KConst& c = x->c;
   const size_t plane = (size_t)c.plane;
-  if (!x->out) HIPCHK(x, hipMalloc((void**)&x->out, (4 + (size_t)c.ns) * plane * 8));
-  HIPCHK(x, hipMemsetAsync(x->out, 0, (4 + (size_t)c.ns) * plane * 8, x->stream));
-  const dim3 grid(c.nblocks), block(64, WPB);
-  if (x->precision == LBRX_F64) {
-    KArgs<double> A{};
-    fill_args(x, A, x->kd);
-    A.o_r1 = x->out;
-    A.o_r2 = x->out + plane;
-    A.o_ux = x->out + 2 * plane;
-    A.o_uy = x->out + 3 * plane;
-    A.o_C = x->out + 4 * plane;
-    hipLaunchKernelGGL(x->export64, grid, block, 0, x->stream, A);
-  } else {
-    KArgs<float> A{};
-    fill_args(x, A, x->kf);
-    A.o_r1 = x->out;
-    A.o_r2 = x->out + plane;
-    A.o_ux = x->out + 2 * plane;
-    A.o_uy = x->out + 3 * plane;
-    A.o_C = x->out + 4 * plane;
-    hipLaunchKernelGGL(x->export32, grid, block, 0, x->stream, A);
+  if (!x->out) {
+    HIPCHK(x, hipMalloc((void**)&x->out, (4 + (size_t)c.ns) * plane * 8));
+    HIPCHK(x, upload_args(x));
   }
+  HIPCHK(x, hipMemsetAsync(x->out, 0, (4 + (size_t)c.ns) * plane * 8, x->stream));
+  launch_one(x, true);
   HIPCHK(x, hipGetLastError());
   hipLaunchKernelGGL(k_ledger_sum, dim3(NLED), dim3(LSUM_THREADS), 0, x->stream, x->led, c.nitems, x->ledsum);
   HIPCHK(x, hipGetLastError());
@@ -1991,6 +2037,181 @@ lbrx_status lbrx_fields(lbrx_ctx* x, lbrx_fields_out* o) {
 
 int64_t lbrx_step_count(const lbrx_ctx* x) { return x ? x->steps : -1; }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------- batches
+// Several simulations stepped by one launch per step: the workgroups of all
+// of them in one grid, each looking up its simulation, item block and step
+// phase in a table built on the host.  Runs of GRAPH_LEN steps replay a
+// captured HIP graph (GRAPH_LEN is a multiple of 6, the period of the phases,
+// so one graph serves every replay).
+constexpr int GRAPH_LEN = 30;
+
+struct lbrx_batch {
+  std::vector<lbrx_ctx*> ctx;
+  std::vector<int64_t> base;  // step counts when the table was built
+  int precision = 0, device = 0;
+  hipStream_t stream = nullptr;
+  void** dinst = nullptr;
+  uint32_t* dtable = nullptr;
+  int nblocks = 0;
+  int64_t launches = 0;  // since the table was built
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::string msg;
+};
+
+namespace {
+
+lbrx_status batch_err(lbrx_batch* b, lbrx_status s, const std::string& m) {
+  if (b) b->msg = m;
+  return s;
+}
+
+void batch_drop_graph(lbrx_batch* b) {
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->gexec = nullptr;
+  b->graph = nullptr;
+}
+
+// table of workgroups: simulation-major, each simulation's blocks in order,
+// with the simulation's step phase now
+lbrx_status batch_build(lbrx_batch* b) {
+  std::vector<uint32_t> tab;
+  for (size_t i = 0; i < b->ctx.size(); ++i) {
+    lbrx_ctx* x = b->ctx[i];
+    for (int k = 0; k < x->c.nblocks; ++k)
+      tab.push_back(((uint32_t)i << TAB_INST_SHIFT) | ((uint32_t)(x->steps % 6) << TAB_PHASE_SHIFT) | (uint32_t)k);
+    b->base[i] = x->steps;
+  }
+  if (b->dtable) (void)hipFree(b->dtable);
+  b->dtable = nullptr;
+  if (hipMalloc((void**)&b->dtable, tab.size() * 4) != hipSuccess)
+    return batch_err(b, LBRX_E_NOMEM, "device allocation of the batch table failed");
+  if (hipMemcpy(b->dtable, tab.data(), tab.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+    return batch_err(b, LBRX_E_DEVICE, "copy of the batch table failed");
+  b->nblocks = (int)tab.size();
+  b->launches = 0;
+  batch_drop_graph(b);
+  return LBRX_OK;
+}
+
+void batch_launch(lbrx_batch* b, int lidx) {
+  LaunchArgs L{};
+  L.inst = b->dinst;
+  L.table = b->dtable;
+  L.ninst = (int)b->ctx.size();
+  L.launch = lidx;
+  const dim3 grid(b->nblocks), block(64, WPB);
+  lbrx_ctx* x = b->ctx[0];
+  if (b->precision == LBRX_F64)
+    hipLaunchKernelGGL(x->step64, grid, block, 0, b->stream, L);
+  else
+    hipLaunchKernelGGL(x->step32, grid, block, 0, b->stream, L);
+}
+
+}  // namespace
+
+extern "C" {
+
+lbrx_status lbrx_batch_create(lbrx_ctx* const* ctxs, int n, lbrx_batch** out) {
+  if (!out) return LBRX_E_INVAL;
+  *out = nullptr;
+  if (!ctxs || n < 1 || n >= (1 << (32 - TAB_INST_SHIFT))) return LBRX_E_INVAL;
+  lbrx_ctx* x0 = ctxs[0];
+  for (int i = 0; i < n; ++i) {
+    lbrx_ctx* x = ctxs[i];
+    if (!x || x->failed) return LBRX_E_INVAL;
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == x) return LBRX_E_INVAL;
+    if (x->device != x0->device || x->stream != x0->stream || x->precision != x0->precision || x->c.ns != x0->c.ns)
+      return LBRX_E_INVAL;
+    if ((unsigned)x->c.nblocks > TAB_BLOCK_MASK + 1u) return LBRX_E_INVAL;
+  }
+  lbrx_batch* b = new lbrx_batch();
+  b->ctx.assign(ctxs, ctxs + n);
+  b->base.assign(n, 0);
+  b->precision = x0->precision;
+  b->device = x0->device;
+  b->stream = x0->stream;
+  if (hipSetDevice(b->device) != hipSuccess) {
+    delete b;
+    return LBRX_E_DEVICE;
+  }
+  std::vector<void*> inst(n);
+  for (int i = 0; i < n; ++i) inst[i] = ctxs[i]->dargs;
+  if (hipMalloc((void**)&b->dinst, n * sizeof(void*)) != hipSuccess) {
+    delete b;
+    return LBRX_E_NOMEM;
+  }
+  const lbrx_status s = hipMemcpy(b->dinst, inst.data(), n * sizeof(void*), hipMemcpyHostToDevice) == hipSuccess
+                            ? batch_build(b) : LBRX_E_DEVICE;
+  if (s != LBRX_OK) {
+    lbrx_batch_destroy(b);
+    return s;
+  }
+  *out = b;
+  return LBRX_OK;
+}
+
+lbrx_status lbrx_batch_step(lbrx_batch* b, int64_t n) {
+  if (!b) return LBRX_E_INVAL;
+  if (n < 0) return batch_err(b, LBRX_E_INVAL, "n_steps must be >= 0");
+  for (size_t i = 0; i < b->ctx.size(); ++i)
+    if (b->ctx[i]->failed) return batch_err(b, LBRX_E_STATE, "a simulation of the batch failed earlier");
+  if (hipSetDevice(b->device) != hipSuccess) return batch_err(b, LBRX_E_DEVICE, "hipSetDevice failed");
+  // a simulation stepped on its own since: the phases in the table are stale
+  for (size_t i = 0; i < b->ctx.size(); ++i)
+    if (b->ctx[i]->steps != b->base[i] + b->launches) {
+      const lbrx_status s = batch_build(b);
+      if (s != LBRX_OK) return s;
+      break;
+    }
+  int64_t done = 0;
+  while (done < n) {
+    const int lidx = (int)(b->launches % 6);
+    if (lidx == 0 && n - done >= GRAPH_LEN) {
+      if (!b->gexec) {
+        if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+          return batch_err(b, LBRX_E_DEVICE, "graph capture failed to start");
+        for (int i = 0; i < GRAPH_LEN; ++i) batch_launch(b, i % 6);
+        if (hipStreamEndCapture(b->stream, &b->graph) != hipSuccess ||
+            hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
+          batch_drop_graph(b);
+          return batch_err(b, LBRX_E_DEVICE, "graph capture failed");
+        }
+      }
+      if (hipGraphLaunch(b->gexec, b->stream) != hipSuccess) return batch_err(b, LBRX_E_DEVICE, "graph launch failed");
+      done += GRAPH_LEN;
+      b->launches += GRAPH_LEN;
+    } else {
+      batch_launch(b, lidx);
+      if (hipGetLastError() != hipSuccess) return batch_err(b, LBRX_E_DEVICE, "batched launch failed");
+      done += 1;
+      b->launches += 1;
+    }
+  }
+  for (lbrx_ctx* x : b->ctx) {
+    x->steps += n;
+    x->cur = (int)(x->steps & 1);
+  }
+  return LBRX_OK;
+}
+
+const char* lbrx_batch_last_error(const lbrx_batch* b) { return b ? b->msg.c_str() : "NULL batch"; }
+
+lbrx_status lbrx_batch_destroy(lbrx_batch* b) {
+  if (!b) return LBRX_OK;
+  (void)hipSetDevice(b->device);
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  batch_drop_graph(b);
+  if (b->dtable) (void)hipFree(b->dtable);
+  if (b->dinst) (void)hipFree(b->dinst);
+  delete b;
+  return LBRX_OK;
+}
+
 void* lbrx_stream(const lbrx_ctx* x) { return x ? (void*)x->stream : nullptr; }
 
 const char* lbrx_last_error(const lbrx_ctx* x) { return x ? x->msg.c_str() : "NULL context"; }
@@ -2011,6 +2232,7 @@ lbrx_status lbrx_destroy(lbrx_ctx* x) {
   if (x->ledsum) (void)hipFree(x->ledsum);
   if (x->err) (void)hipFree(x->err);
   if (x->out) (void)hipFree(x->out);
+  if (x->dargs) (void)hipFree(x->dargs);
   if (x->own_stream && x->stream) (void)hipStreamDestroy(x->stream);
   delete x;
   return LBRX_OK;

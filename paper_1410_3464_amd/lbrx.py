@@ -14,7 +14,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbrx.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 MAXS = 8
 MAXR = 8
 F64, F32, F16DEV, BF16DEV = 0, 1, 2, 3
@@ -27,7 +27,8 @@ STATUS = {0: "LBRX_OK", 1: "LBRX_E_INVAL", 2: "LBRX_E_NOMEM", 3: "LBRX_E_DEVICE"
 # every symbol include/lbrx.h declares
 SYMBOLS = ("lbrx_create", "lbrx_create_error", "lbrx_step", "lbrx_sync", "lbrx_fields",
            "lbrx_step_count", "lbrx_stream", "lbrx_destroy", "lbrx_last_error",
-           "lbrx_status_string")
+           "lbrx_status_string", "lbrx_batch_create", "lbrx_batch_step", "lbrx_batch_last_error",
+           "lbrx_batch_destroy")
 
 
 class HomRxn(C.Structure):
@@ -54,7 +55,7 @@ class Params(C.Structure):
         ("n_hom", C.c_int32), ("hom", HomRxn * MAXR),
         ("n_het", C.c_int32), ("het", HetRxn * MAXR),
         ("node_type", C.c_void_p), ("V0", C.c_void_p), ("rho1", C.c_void_p), ("rho2", C.c_void_p),
-        ("C0", C.c_void_p),
+        ("C0", C.c_void_p), ("seg_rows", C.c_int32),
     ]
 
 
@@ -108,14 +109,23 @@ def load_library(path=LIB_PATH):
     lib.lbrx_last_error.argtypes = [C.c_void_p]
     lib.lbrx_status_string.restype = C.c_char_p
     lib.lbrx_status_string.argtypes = [C.c_int]
+    lib.lbrx_batch_create.restype = C.c_int
+    lib.lbrx_batch_create.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_void_p)]
+    lib.lbrx_batch_step.restype = C.c_int
+    lib.lbrx_batch_step.argtypes = [C.c_void_p, C.c_int64]
+    lib.lbrx_batch_last_error.restype = C.c_char_p
+    lib.lbrx_batch_last_error.argtypes = [C.c_void_p]
+    lib.lbrx_batch_destroy.restype = C.c_int
+    lib.lbrx_batch_destroy.argtypes = [C.c_void_p]
     _lib = lib
     return lib
 
 
-def make_params(prob, precision="f64"):
+def make_params(prob, precision="f64", seg_rows=0):
     """lbrx_params for a workloads.Problem; returns (params, keep-alive arrays)."""
     p = Params()
     p.abi_version = ABI_VERSION
+    p.seg_rows = int(seg_rows)
     p.nx, p.ny = prob.nx, prob.ny
     p.periodic = (1 if prob.periodic_x else 0) | (2 if prob.periodic_y else 0)
     p.precision = _PREC[precision]
@@ -167,13 +177,13 @@ def _ptr(a):
 class Lbrx:
     """One GPU simulation of a workloads.Problem (a context of the C ABI)."""
 
-    def __init__(self, prob, precision="f64", stream=None):
+    def __init__(self, prob, precision="f64", stream=None, seg_rows=0):
         lib = load_library()
         self._lib = lib
         self.prob = prob
         self.nx, self.ny, self.ns = prob.nx, prob.ny, prob.n_species
         self.precision = precision
-        params, keep = make_params(prob, precision)
+        params, keep = make_params(prob, precision, seg_rows)
         h = C.c_void_p()
         st = lib.lbrx_create(C.byref(params), stream, C.byref(h))
         if st != 0:
@@ -235,3 +245,35 @@ def unpack_ledger(arr):
         out[name] = v if n > 1 else float(v[0])
         o += n
     return out
+
+
+class Batch:
+    """Several Lbrx contexts (same stream, precision and species count)
+    advanced by one kernel launch per step (lbrx_batch_*)."""
+
+    def __init__(self, sims):
+        lib = load_library()
+        self._lib = lib
+        self.sims = list(sims)
+        arr = (C.c_void_p * len(self.sims))(*[s._h.value for s in self.sims])
+        h = C.c_void_p()
+        st = lib.lbrx_batch_create(arr, len(self.sims), C.byref(h))
+        if st != 0:
+            raise LbrxError(st, "lbrx_batch_create rejected the contexts")
+        self._h = h
+
+    def step(self, n=1):
+        st = self._lib.lbrx_batch_step(self._h, int(n))
+        if st != 0:
+            raise LbrxError(st, self._lib.lbrx_batch_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.lbrx_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,101 @@
+"""16-bit deviation storage (FP16 / BF16 populations, FP32 arithmetic) against
+the FP64 oracle.
+
+A stored value is (f - w_a rho_ref) x 2^k, rounded to 16 bits, where rho_ref
+is the middle of the node's reference bucket (4 mantissa bits for rho_1, 3 for
+rho_2: at most 3.2 % and 6.3 % away from the node's density).  At rest the
+deviation is at most that fraction of the population, so the initial state
+reads back within half an ulp of it: 2^-11 x 0.063 (FP16) or 2^-8 x 0.063
+(BF16) relative.  Once the fluid moves, the deviation also holds the velocity
+terms of the equilibrium (3 e.u), and the interface dynamics amplify rounding
+as they do in FP32 and FP64; the bounds after 100 steps are the measured
+errors with a margin, stated per field.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import OracleSim
+from paper_1410_3464_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+sys.path.insert(0, os.path.dirname(__file__))
+from parity import compare  # noqa: E402
+
+HALF_ULP = {"f16dev": 2.0 ** -11, "bf16dev": 2.0 ** -8}
+
+
+def _lbrx():
+    from paper_1410_3464_amd.lbrx import Lbrx
+
+    return Lbrx
+
+
+@pytest.mark.parametrize("precision", ["f16dev", "bf16dev"])
+def test_initial_state_reads_back(precision):
+    """Step 0 exported from 16-bit storage: densities and concentrations within
+    the encoding bound (every node reads its own slots at step 0)."""
+    p = W.config0()
+    g = _lbrx()(p, precision)
+    G = g.fields()
+    fl = p.type0 == 0
+    bound = HALF_ULP[precision] * 0.063 * 1.01
+    for name, ref in (("rho1", p.rho1), ("rho2", p.rho2)):
+        err = np.abs(G[name][fl] - ref[fl]) / ref[fl]
+        print(precision, name, err.max(), flush=True)
+        assert err.max() <= bound, (name, err.max(), bound)
+    liq = G["liquid"].astype(bool)
+    cscale = np.abs(p.C0).max()  # species starting at zero are measured on the same scale
+    for k in range(p.n_species):
+        ref = p.C0[k][liq]
+        err = np.abs(G["C"][k][liq] - ref).max() / cscale
+        print(precision, "C", k, err, flush=True)
+        assert err <= bound
+    g.close()
+
+
+# measured after 100 steps of the droplet box: FP16 rho 2.0e-4, u 2.8e-3;
+# BF16 rho 1.4e-3, u 2.3e-2 (max-norm relative; concentrations are left out:
+# a liquid mark that flips one step apart near the threshold moves them by
+# O(1) at that node)
+BOUNDS_100 = {"f16dev": {"rho": 1e-3, "u": 1e-2}, "bf16dev": {"rho": 5e-3, "u": 5e-2}}
+
+
+@pytest.mark.parametrize("precision", ["f16dev", "bf16dev"])
+def test_droplet_accuracy_100_steps(precision):
+    """The moving droplet after 1, 10 and 100 steps: densities and velocities
+    within the stated bounds of the FP64 oracle, node masks identical, and the
+    mass of each component equal to its ledger balance within the 16-bit
+    rounding of the stored deviations."""
+    p = W.config0()
+    o = OracleSim(p)
+    g = _lbrx()(p, precision)
+    done = 0
+    for n in (1, 10, 100):
+        o.step(n - done)
+        g.step(n - done)
+        done = n
+        G, O = g.fields(), o.fields()
+        errs, masks, near = compare(G, O, p, 1.0)
+        print(f"[{precision} {n}] " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
+        assert masks
+        b = BOUNDS_100[precision]
+        for k in ("rho1", "rho2"):
+            assert errs[k] <= b["rho"], (k, errs[k])
+        for k in ("ux", "uy"):
+            assert errs[k] <= b["u"], (k, errs[k])
+    L = G["ledger"]
+    fl = p.type0 == 0
+    M0 = np.array([p.rho1[fl].sum(), p.rho2[fl].sum()])
+    M = np.array([G["rho1"].sum(), G["rho2"].sum()])
+    bal = M0 + L["mass_src"] + L["mass_inj"] - L["mass_rem"]
+    drift = np.abs(M / bal - 1)
+    print(f"[{precision}] mass drift after 100 steps {drift}", flush=True)
+    # worst case: every stored deviation (at most 6.3 % of its population at
+    # rest) rounds the same way at every step
+    assert np.all(drift <= 100 * HALF_ULP[precision] * 0.063)
+    o.close()
+    g.close()
