@@ -78,6 +78,26 @@ def measured_traffic(precision, n):
     return rec["traffic_bytes_per_launch"]
 
 
+def serving(n, interarrival):
+    """Poisson arrivals of many-simulation requests (square porous lattices of
+    side 64-1024, 200-2000 steps, FP32 or FP16-deviation storage), served by
+    the batched loop and, for comparison, one at a time with plain runs."""
+    from paper_1410_3464_amd import serve
+
+    reqs = serve.poisson_requests(n, interarrival, seed=11)
+    batched = serve.Server(tick=60).run(reqs)
+    plain = serve.run_plain(serve.clone_requests(reqs))
+    print(f"# serving batched {batched} plain {plain}", file=sys.stderr, flush=True)
+    return {
+        "workload": f"{n} requests, Poisson arrivals every {interarrival * 1e3:.0f} ms on average, "
+                    "porous lattices 64^2-1024^2, 200-2000 steps, f32 or f16dev",
+        "batched": batched, "plain": plain,
+        "p50_speedup": round(plain["p50_ms"] / batched["p50_ms"], 2),
+        "p99_speedup": round(plain["p99_ms"] / batched["p99_ms"], 2),
+        "mlups_ratio": round(batched["mlups"] / plain["mlups"], 2),
+    }
+
+
 def cpu_baseline(prob, steps):
     """The FP64 oracle, as it stands, single-threaded on the host: `steps` steps of
     the same lattice."""
@@ -102,6 +122,9 @@ def main():
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=48,
+                    help="requests of the serving comparison (0: skip it)")
+    ap.add_argument("--serve-interarrival-ms", type=float, default=15.0)
     ap.add_argument("--copy-probe-gb", type=float, default=0.0,
                     help="run a plain device-to-device copy of this many GB first (counter calibration)")
     args = ap.parse_args()
@@ -201,6 +224,8 @@ def main():
     }
     sim.close()
     del sim
+    if args.serve_requests > 0:
+        out["serving"] = serving(args.serve_requests, args.serve_interarrival_ms / 1e3)
     if not args.no_cpu:
         cpu_mlups, dt = cpu_baseline(prob, args.cpu_steps)
         out["cpu_baseline"] = {

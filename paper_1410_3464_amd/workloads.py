@@ -252,15 +252,16 @@ def porous_medium(nx, ny, seed, porosity=0.55, rmin=8.0, rmax=24.0, reactive_fra
     return type0, gas, rng
 
 
-def config1(nx=1024, ny=512, seed=1, steps=20000):
+def config1(nx=1024, ny=512, seed=1, steps=20000, porosity=0.55, rates=(1e-1, 1e-5, 1e-3, 1e-4)):
     """Porous medium: porosity 0.55, 20% of solid dissolvable, 30% of the pore space
     vapour bubbles, body force 1e-6 along x, periodic in x with walls in y; species
     A, B, E, F with A <-> B + C(g) (k1 = 0.1, K_eq = 1, M_C = 1e-3), B + E -> F
     (k3 = 1e-5), surface dissolution of D by B -> E (1e-3) and precipitation of F on
-    D or F (1e-4, C_sa = 0)."""
+    D or F (1e-4, C_sa = 0).  `rates` are (k1, k3, dissolution, precipitation)."""
     a, b, R = EOS_PAPER
     T = 0.75 * critical_temperature(a, b, R)
-    type0, gas, rng = porous_medium(nx, ny, seed)
+    k1, k3, kd, kp = rates
+    type0, gas, rng = porous_medium(nx, ny, seed, porosity=porosity)
     fl = type0 == FLUID
     rho1 = np.where(gas, RHO_V_075_PAPER, RHO_L_075_PAPER)
     rho2 = np.full((ny, nx), 0.1)
@@ -276,12 +277,12 @@ def config1(nx=1024, ny=512, seed=1, steps=20000):
         tau=(1.0, 1.0), gbody=(1e-6, 0.0), a=a, b=b, R=R, T=T, G11=-1.0, G12=0.5, G21=0.5,
         a0=0.005, rho10=paper_rho10(0.005), rho20=0.003,
         species=[Species("A"), Species("B"), Species("E"), Species("F")],
-        hom=[HomRxn("r1_gas", re=(0, -1), pr=(1, -1), k=1e-1, K_eq=1.0, M_gas=1e-3),
-             HomRxn("bimolecular", re=(1, 2), pr=(3, -1), k=1e-5)],
+        hom=[HomRxn("r1_gas", re=(0, -1), pr=(1, -1), k=k1, K_eq=1.0, M_gas=1e-3),
+             HomRxn("bimolecular", re=(1, 2), pr=(3, -1), k=k3)],
         het=[HetRxn(reactant=1, product=2, surface=(SOLID_D,), mode="consumes",
-                    irreversible=True, k=1e-3, C_eq=0.0, molar_volume=1.0),
+                    irreversible=True, k=kd, C_eq=0.0, molar_volume=1.0),
              HetRxn(reactant=3, product=-1, surface=(SOLID_D, SOLID_F), mode="grows",
-                    irreversible=True, k=1e-4, C_eq=0.0, molar_volume=1.0)],
+                    irreversible=True, k=kp, C_eq=0.0, molar_volume=1.0)],
         type0=type0, V0=V0, rho1=rho1, rho2=rho2, C0=C0, steps=steps,
     )
 
@@ -290,6 +291,20 @@ def config2(n=4096, seed=2, steps=10000):
     """The porous-medium generator at 4096 x 4096 (the throughput workload)."""
     p = config1(nx=n, ny=n, seed=seed, steps=steps)
     p.name = f"porous-{n}x{n}"
+    return p
+
+
+def batch_instance(seed, smin=64, smax=1024):
+    """One instance of the many-simulations workload: the porous-medium
+    generator on a square lattice whose side is log-uniform in [smin, smax],
+    porosity uniform in [0.4, 0.8], each of the four rate constants log-uniform
+    in [1e-6, 1e-1]."""
+    rng = _rng(10_000 + seed)
+    side = int(round(np.exp(rng.uniform(np.log(smin), np.log(smax)))))
+    porosity = float(rng.uniform(0.4, 0.8))
+    rates = tuple(float(np.exp(rng.uniform(np.log(1e-6), np.log(1e-1)))) for _ in range(4))
+    p = config1(nx=side, ny=side, seed=seed, porosity=porosity, rates=rates)
+    p.name = f"batch-{seed}-{side}x{side}"
     return p
 
 

@@ -1,0 +1,45 @@
+"""The serving loop: requests served in the batched mix give the same result as
+each request run alone, and the loop reports latencies and throughput."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("rho1", "rho2", "ux", "uy", "C", "V", "type", "liquid")
+
+
+def test_mix_equals_alone():
+    """Eight requests of different sizes, step counts and precisions arrive
+    while others run; each request's fields equal, bit for bit, those of the
+    same request run alone (the node values do not depend on the batching or
+    on the autotuned work decomposition; the balance sums, added per work
+    item, agree to rounding)."""
+    from paper_1410_3464_amd import serve
+
+    reqs = serve.poisson_requests(8, 0.004, seed=7, steps=(40, 120), sizes=(64, 160))
+    mixed = serve.Server(tick=25, keep_fields=True).run(reqs)
+    alone_reqs = serve.clone_requests(reqs)
+    plain = serve.run_plain(alone_reqs, keep_fields=True)
+    print("mixed", mixed, "plain", plain, flush=True)
+    assert mixed["completed"] == plain["completed"] == len(reqs)
+    for a, b in zip(reqs, alone_reqs):
+        for k in KEYS:
+            assert np.array_equal(a.fields[k], b.fields[k]), (a.rid, a.precision, k)
+        for k, v in b.fields["ledger"].items():
+            np.testing.assert_allclose(a.fields["ledger"][k], v, rtol=1e-6, atol=1e-9)
+    for r in reqs:
+        assert r.arrival <= r.start <= r.finish
+
+
+def test_admission_respects_memory_cap():
+    """With a cap that holds only one of the requests at a time the server runs
+    them one after the other and still completes all of them."""
+    from paper_1410_3464_amd import serve
+
+    reqs = serve.poisson_requests(4, 0.001, seed=3, steps=(30, 60), sizes=(64, 96))
+    cap = max(serve.footprint_bytes(r.prob, r.precision) for r in reqs) * 1.01
+    s = serve.Server(hbm_cap=cap, tick=10, autotune=False).run(reqs)
+    assert s["completed"] == 4
+    spans = sorted((r.start, r.finish) for r in reqs)
+    for (s0, f0), (s1, f1) in zip(spans, spans[1:]):
+        assert s1 >= f0 - 1e-3
