@@ -527,6 +527,17 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
         f[1][a] = q.hi;
       }
     };
+    // Zeroed before the branches, not in an else: stores to the same array
+    // on both sides of a branch get merged into one store through a pointer
+    // select, which sends the whole array to scratch memory.
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int a = 0; a < 9; ++a) f[s][a] = T(0);
+#pragma unroll
+    for (int kk = 0; kk < NSA; ++kk)
+#pragma unroll
+      for (int a = 0; a < 5; ++a) g[kk][a] = T(0);
     if (validf) {
       const unsigned own = co[1] + ur[1] * RSF;
       fin(0, own);
@@ -536,11 +547,6 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
         const bool src = (w >> (NBF_SHIFT + b - 1)) & 1u;
         fin(a, src ? co[ex(b) + 1] + (ur[ey(b) + 1] * RSF + (unsigned)a * PS) : own + (unsigned)b * PS);
       }
-    } else {
-#pragma unroll
-      for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int a = 0; a < 9; ++a) f[s][a] = T(0);
     }
     if (NS > 0 && liqp) {
       const unsigned own = co[1] + ur[1] * RSG;
@@ -577,11 +583,6 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
         const bool src = (w >> (NBL_SHIFT + b - 1)) & 1u;
         gin(a, src ? co[ex(b) + 1] + (ur[ey(b) + 1] * RSG + (unsigned)a * PS) : own + (unsigned)b * PS);
       }
-    } else {
-#pragma unroll
-      for (int kk = 0; kk < NSA; ++kk)
-#pragma unroll
-        for (int a = 0; a < 5; ++a) g[kk][a] = T(0);
     }
   };
 
