@@ -8,8 +8,11 @@ are resident in HBM before the timed region starts.
 
 Prints one JSON line: MLUPS (nx*ny*steps/s/1e6), the HBM roofline of the step
 kernel (algorithmic bytes per launch / kernel time from HIP events on the
-library's stream), and the FP64 CPU oracle timed on a bounded sample of the
-same lattice on the host cores.
+library's stream), the FP64 CPU oracle timed on a bounded sample of the same
+lattice on the host cores, and two many-simulation comparisons: 256 porous
+instances stepped together by batched launches against one at a time
+("batched"), and Poisson-arriving requests served by the continuous-batching
+loop against plain one-at-a-time runs ("serving").
 """
 import argparse
 import json
@@ -98,6 +101,64 @@ def serving(n, interarrival):
     }
 
 
+def batched(n_inst, steps, warmup=30, plain_warmup=5):
+    """Many independent simulations: n_inst FP32 instances of the porous-medium
+    generator (square sides log-uniform in 64-1024, porosity uniform in
+    0.4-0.8, rate constants log-uniform in 1e-6-1e-1), advanced together by one
+    launch per step (HIP graphs of 30 steps; item heights from the autotuner),
+    against the same instances run one after the other, each alone with the
+    default item height.  Both sides time `steps` steps per instance after
+    warm-up steps; creating the simulations is outside the timed regions."""
+    import torch
+
+    from paper_1410_3464_amd import workloads as W
+    from paper_1410_3464_amd.autotune import table, tuned_seg_rows
+    from paper_1410_3464_amd.lbrx import Batch, Lbrx
+
+    probs = [W.batch_instance(50_000 + i) for i in range(n_inst)]
+    nodes = sum(p.nx * p.ny for p in probs)
+    st = torch.cuda.Stream()
+    seg = [tuned_seg_rows(p, "f32", st) for p in probs]
+    sims = [Lbrx(p, "f32", stream=st.cuda_stream, seg_rows=h) for p, h in zip(probs, seg)]
+    b = Batch(sims)
+    b.step(warmup)
+    st.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    st.synchronize()
+    wall_b = time.perf_counter() - t0
+    b.close()
+    for s in sims:
+        s.sync()  # raises on a numerical failure
+        s.close()
+    del sims
+    print(f"# batched: {n_inst} instances, {nodes} nodes, {wall_b / steps * 1e3:.3f} ms per step",
+          file=sys.stderr, flush=True)
+    wall_p = 0.0
+    for p in probs:
+        s = Lbrx(p, "f32", stream=st.cuda_stream)
+        s.step(plain_warmup)
+        st.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps)
+        st.synchronize()
+        wall_p += time.perf_counter() - t0
+        s.sync()
+        s.close()
+    mb = nodes * steps / wall_b / 1e6
+    mp = nodes * steps / wall_p / 1e6
+    print(f"# batched {mb:.1f} MLUPS, one at a time {mp:.1f} MLUPS", file=sys.stderr, flush=True)
+    return {
+        "workload": f"{n_inst} FP32 porous instances, sides log-uniform 64-1024 "
+                    f"({nodes} nodes in all), {steps} timed steps each",
+        "batched_mlups": round(mb, 1), "one_at_a_time_mlups": round(mp, 1),
+        "ratio": round(mb / mp, 2),
+        "batched_ms_per_step": round(wall_b / steps * 1e3, 3),
+        "one_at_a_time_s": round(wall_p, 3),
+        "seg_rows_by_size_class": {f"{k[0]}": v for k, v in table().items() if k[1] == "f32"},
+    }
+
+
 def cpu_baseline(prob, steps):
     """The FP64 oracle, as it stands, single-threaded on the host: `steps` steps of
     the same lattice."""
@@ -125,6 +186,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=48,
                     help="requests of the serving comparison (0: skip it)")
     ap.add_argument("--serve-interarrival-ms", type=float, default=15.0)
+    ap.add_argument("--batch-instances", type=int, default=256,
+                    help="instances of the many-simulations comparison (0: skip it)")
+    ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--copy-probe-gb", type=float, default=0.0,
                     help="run a plain device-to-device copy of this many GB first (counter calibration)")
     args = ap.parse_args()
@@ -224,6 +288,8 @@ def main():
     }
     sim.close()
     del sim
+    if args.batch_instances > 0:
+        out["batched"] = batched(args.batch_instances, args.batch_steps)
     if args.serve_requests > 0:
         out["serving"] = serving(args.serve_requests, args.serve_interarrival_ms / 1e3)
     if not args.no_cpu:
