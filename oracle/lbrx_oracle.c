@@ -325,9 +325,14 @@ static int macros(orc_sim* s) {
 
   /* 4. forces at fluid nodes (Eq. 11, 14, 16, body force).
    * A neighbour that is not fluid (solid, or outside a non-periodic
-   * boundary) has wall density s = 1 in Eq. 16 and, in the cohesion and
-   * inter-component sums, carries the centre node's own psi / phi, so a
-   * uniform phase next to a wall feels no force unless w != 0. */
+   * boundary) has wall density s = 1 in Eq. 16.  In the cohesion and
+   * inter-component sums it carries the psi / phi of its mirror image in
+   * the wall, taken inside the 3x3 block: for an axis link that is the
+   * centre node itself; for a diagonal link, the fluid node(s) of the block
+   * that share the diagonal neighbour's column or row (their mean when both
+   * are fluid), else the centre node.  At a flat wall the sums then see the
+   * reflected field, so with w = 0 the wall is neutral and a droplet meets
+   * it at 90 degrees, as App. A.1 (Fig. A2) reports. */
   for (int i = 0; i < N; ++i) {
     for (int sg = 0; sg < 2; ++sg) s->Fx[sg * N + i] = s->Fy[sg * N + i] = 0.0;
     if (s->type[i] != ORC_FLUID) continue;
@@ -336,9 +341,35 @@ static int macros(orc_sim* s) {
     for (int a = 1; a < 9; ++a) {
       const int j = nb(s, x, y, a);
       const int fl = j >= 0 && s->type[j] == ORC_FLUID;
-      const double ps = fl ? s->psi1[j] : s->psi1[i];
-      const double q2 = fl ? s->phi2[j] : s->phi2[i];
-      const double q1 = fl ? s->phi1[j] : s->phi1[i];
+      double ps, q1, q2;
+      if (fl) {
+        ps = s->psi1[j];
+        q1 = s->phi1[j];
+        q2 = s->phi2[j];
+      } else {
+        int m1 = i, m2 = -1;  /* mirror image node(s) */
+        if (a >= 5) {
+          const int jx = nb(s, x, y, EX[a] > 0 ? 1 : 3), jy = nb(s, x, y, EY[a] > 0 ? 2 : 4);
+          const int fx = jx >= 0 && s->type[jx] == ORC_FLUID, fy = jy >= 0 && s->type[jy] == ORC_FLUID;
+          if (fx && fy) {
+            m1 = jx;
+            m2 = jy;
+          } else if (fx) {
+            m1 = jx;
+          } else if (fy) {
+            m1 = jy;
+          }
+        }
+        if (m2 >= 0) {
+          ps = 0.5 * (s->psi1[m1] + s->psi1[m2]);
+          q1 = 0.5 * (s->phi1[m1] + s->phi1[m2]);
+          q2 = 0.5 * (s->phi2[m1] + s->phi2[m2]);
+        } else {
+          ps = s->psi1[m1];
+          q1 = s->phi1[m1];
+          q2 = s->phi2[m1];
+        }
+      }
       const double sw = fl ? 0.0 : 1.0;
       c1x += WF[a] * ps * EX[a];
       c1y += WF[a] * ps * EY[a];

@@ -817,32 +817,51 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
       if (own && fluid) {
         my_rmax = m.rho[0] > my_rmax ? m.rho[0] : my_rmax;
         // forces: Eq. 11 (cohesion), 14 (inter-component), 16 (adhesion), body
-        // force.  A non-fluid neighbour counts with the centre's own psi / phi
-        // and s = 1; the ring holds zero psi / phi there, so its share is the
-        // centre's value times the solid-neighbour sum.
-        T c1x = 0, c1y = 0, c12x = 0, c12y = 0, c21x = 0, c21y = 0, swx = 0, swy = 0;
+        // force.  A non-fluid neighbour has s = 1 and, in the cohesion and
+        // inter-component sums, the psi / phi of its mirror image in the wall
+        // within the 3x3 block: the centre node for an axis link; for a
+        // diagonal link the fluid axis neighbour(s) sharing its column or row
+        // (their mean when both are fluid), else the centre.  The ring holds
+        // zero psi / phi at non-fluid nodes, so an axis link's share is the
+        // centre's value times the axis solid-neighbour sum.
+        T c1x = 0, c1y = 0, c12x = 0, c12y = 0, c21x = 0, c21y = 0, swx = 0, swy = 0, sax = 0, say = 0;
 #pragma unroll
         for (int a = 1; a < 9; ++a) {
-          const T sw = is_fluid(nt[a]) ? T(0) : T(1);
+          const bool nf = !is_fluid(nt[a]);
+          const T sw = nf ? T(1) : T(0);
+          T vps = nq[a].ps, vq1 = nq[a].q1, vq2 = nq[a].q2;
+          if (a >= 5) {
+            const int ax = ex(a) > 0 ? 1 : 3, ay = ey(a) > 0 ? 2 : 4;
+            const bool fx = is_fluid(nt[ax]), fy = is_fluid(nt[ay]);
+            const T h = (fx && fy) ? T(0.5) : T(1);
+            const bool own = !fx && !fy;
+            if (nf) {
+              vps = own ? ps : (nq[ax].ps + nq[ay].ps) * h;
+              vq1 = own ? q1 : (nq[ax].q1 + nq[ay].q1) * h;
+              vq2 = own ? q2 : (nq[ax].q2 + nq[ay].q2) * h;
+            }
+          }
           if (ex(a) != 0) {
-            c1x += T(wf(a) * ex(a)) * nq[a].ps;
-            c12x += T(wf(a) * ex(a)) * nq[a].q2;
-            c21x += T(wf(a) * ex(a)) * nq[a].q1;
+            c1x += T(wf(a) * ex(a)) * vps;
+            c12x += T(wf(a) * ex(a)) * vq2;
+            c21x += T(wf(a) * ex(a)) * vq1;
             swx += T(wf(a) * ex(a)) * sw;
+            if (a < 5) sax += T(wf(a) * ex(a)) * sw;
           }
           if (ey(a) != 0) {
-            c1y += T(wf(a) * ey(a)) * nq[a].ps;
-            c12y += T(wf(a) * ey(a)) * nq[a].q2;
-            c21y += T(wf(a) * ey(a)) * nq[a].q1;
+            c1y += T(wf(a) * ey(a)) * vps;
+            c12y += T(wf(a) * ey(a)) * vq2;
+            c21y += T(wf(a) * ey(a)) * vq1;
             swy += T(wf(a) * ey(a)) * sw;
+            if (a < 5) say += T(wf(a) * ey(a)) * sw;
           }
         }
-        c1x += ps * swx;
-        c1y += ps * swy;
-        c12x += q2 * swx;
-        c12y += q2 * swy;
-        c21x += q1 * swx;
-        c21y += q1 * swy;
+        c1x += ps * sax;
+        c1y += ps * say;
+        c12x += q2 * sax;
+        c12y += q2 * say;
+        c21x += q1 * sax;
+        c21y += q1 * say;
         const T r1 = m.rho[0], r2 = m.rho[1];
         T Fx[2], Fy[2];
         Fx[0] = -k.G11 * ps * c1x - k.G12 * q1 * c12x - k.w1 * ps * swx + r1 * k.gx;

@@ -1,0 +1,98 @@
+"""Physical validations of the GPU step at the paper's own sizes.
+
+Equilibrium contact angle against the solid-fluid interaction w (App. A.1,
+Fig. A2): a semicircular droplet on the bottom wall of a 201 x 201 lattice,
+solid walls at top and bottom, periodic left and right, the two-component
+fluid of the paper at density ratio about 150.  The angle is measured from a
+circle fitted to the mid-density contour away from the wall.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_1410_3464_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = json.load(open(os.path.join(HERE, "golden", "paper_printed_values.json")))
+
+
+def droplet_on_wall(n, radius, w):
+    """Liquid component 8.16 inside a half disk centred on the bottom wall
+    (y = -1/2), 0.05 outside; gas component 1e-4 inside, 0.05 outside; the
+    modified Carnahan-Starling set at 0.65 T_c; G12 = G21 = 0.001; adhesion w
+    on the liquid component."""
+    a, b, R = W.EOS_PAPER
+    T = 0.65 * W.critical_temperature(a, b, R)
+    x = np.arange(n)[None, :]
+    y = np.arange(n)[:, None]
+    r = np.hypot(x - n / 2 + 0.5, y + 0.5)
+    out = 0.5 * (1 + np.tanh(2 * (r - radius) / 3.0))
+    rho1 = 0.05 + (8.16 - 0.05) * (1 - out)
+    rho2 = 0.0001 + (0.05 - 0.0001) * out
+    p = W.uniform_problem(n, n, periodic_x=True, periodic_y=False, ideal=False, a=a, b=b, R=R, T=T,
+                          G11=-1.0, G12=0.001, G21=0.001, rho10=W.paper_rho10(), rho20=0.003, a0=0.005,
+                          rho1=1.0, w_adh=(w, 0.0))
+    return p.copy(rho1=rho1, rho2=rho2, name=f"droplet-w{w}")
+
+
+def contact_angle(rho1, ymin=3):
+    """Degrees, from a least-squares circle through the mid-density crossings
+    (along rows and columns, linearly interpolated) at rows >= ymin; the wall
+    lies at y = -1/2 and cos(theta) = (y_wall - y_centre) / radius."""
+    ny, nx = rho1.shape
+    mid = 0.5 * (rho1.max() + rho1.min())
+    pts = []
+    d = rho1 - mid
+    for yy in range(ymin, ny):
+        k = np.nonzero(d[yy, :-1] * d[yy, 1:] < 0)[0]
+        pts += [(kk + d[yy, kk] / (d[yy, kk] - d[yy, kk + 1]), yy) for kk in k]
+    for xx in range(nx):
+        k = np.nonzero(d[ymin:-1, xx] * d[ymin + 1:, xx] < 0)[0] + ymin
+        pts += [(xx, kk + d[kk, xx] / (d[kk, xx] - d[kk + 1, xx])) for kk in k]
+    P = np.array(pts)
+    A = np.c_[2 * P[:, 0], 2 * P[:, 1], np.ones(len(P))]
+    cx, cy, c0 = np.linalg.lstsq(A, (P ** 2).sum(1), rcond=None)[0]
+    rad = math.sqrt(c0 + cx * cx + cy * cy)
+    return math.degrees(math.acos(max(-1.0, min(1.0, (-0.5 - cy) / rad))))
+
+
+def test_contact_angle_against_adhesion():
+    """Five adhesion strengths stepped together (one batched launch per step),
+    FP64, 12,000 steps (angles settled: within 1 degree of those at 6,000).
+    At w = 0 the angle is within 3 degrees of the printed 90; it grows
+    monotonically with w, wetting (< 90) for w < 0.  The printed angles at
+    w = -0.4 (74.2) and 0.14 (97) are not reproduced: the measured slope is
+    about twice the printed one and w >= 0.1 diverges at the contact line
+    (the paper also reports a limited range at this density ratio); the
+    measured values are printed for the record."""
+    import torch
+
+    from paper_1410_3464_amd.lbrx import Batch, Lbrx
+
+    ws = (-0.4, -0.2, -0.1, 0.0, 0.05)
+    n = GOLDEN["contact_angle"]["lattice"][0]
+    st = torch.cuda.Stream()
+    sims = [Lbrx(droplet_on_wall(n, 50.0, w), "f64", stream=st.cuda_stream) for w in ws]
+    b = Batch(sims)
+    b.step(6000)
+    half = [contact_angle(s.fields()["rho1"]) for s in sims]
+    b.step(6000)
+    F = [s.fields() for s in sims]
+    theta = [contact_angle(f["rho1"]) for f in F]
+    b.close()
+    for s in sims:
+        s.close()
+    print("w", ws, "theta(6000)", np.round(half, 2), "theta(12000)", np.round(theta, 2),
+          "printed", dict(zip(GOLDEN["contact_angle"]["w"], GOLDEN["contact_angle"]["theta_deg"])), flush=True)
+    assert np.all(np.abs(np.array(theta) - np.array(half)) < 1.0)
+    i0 = ws.index(0.0)
+    assert abs(theta[i0] - GOLDEN["contact_angle"]["theta_deg"][1]) < 3.0
+    assert np.all(np.diff(theta) > 0)
+    assert theta[0] < 90.0 - 10.0
+    for f in F:
+        assert np.hypot(f["ux"], f["uy"]).max() < 0.1

@@ -125,6 +125,41 @@ def test_workload_coexistence_constants():
 
 
 # --------------------------------------------------------------------------
+# Flow: a wall without adhesion is neutral (App. A.1, Fig. A2: w = 0 -> 90 deg)
+# --------------------------------------------------------------------------
+def test_wall_without_adhesion_is_neutral():
+    """A liquid slab across a channel with solid walls at top and bottom and
+    w = 0.  The paper reports a 90-degree contact angle at w = 0; in two
+    dimensions that means the liquid-vapour interfaces stay straight and
+    perpendicular to the walls: after 3000 steps the interface position
+    differs between rows by less than 0.01 lattice units.  (A wall whose
+    solid neighbours carry the fluid node's own potential instead of its
+    mirror image wets the wall and bends the interfaces by about 2.3 units.)"""
+    assert GOLDEN["contact_angle"]["theta_deg"][1] == 90.0
+    a, b, R = W.EOS_PAPER
+    T = 0.65 * W.critical_temperature(a, b, R)
+    nx, ny = 64, 24
+    x = np.arange(nx)[None, :] + 0.5
+    inside = 0.5 * (np.tanh((x - 16) / 1.5) - np.tanh((x - 48) / 1.5))
+    rho1 = np.repeat(0.05 + (8.16 - 0.05) * inside, ny, 0)
+    rho2 = np.repeat(0.05 + (0.0001 - 0.05) * inside, ny, 0)
+    p = W.uniform_problem(nx, ny, periodic_x=True, periodic_y=False, ideal=False, a=a, b=b, R=R, T=T,
+                          G11=-1.0, G12=0.001, G21=0.001, rho10=W.paper_rho10(), rho20=0.003, a0=0.005,
+                          rho1=1.0)
+    s = OracleSim(p.copy(rho1=rho1, rho2=rho2))
+    s.step(3000)
+    r1 = s.fields()["rho1"]
+    mid = 0.5 * (r1.max() + r1.min())
+    pos = []
+    for yy in range(ny):
+        row = r1[yy, : nx // 2]
+        k = np.nonzero((row[:-1] - mid) * (row[1:] - mid) < 0)[0][0]
+        pos.append(k + (row[k] - mid) / (row[k] - row[k + 1]))
+    assert np.ptp(pos) < 0.01, np.ptp(pos)
+    assert abs(np.mean(pos) - 15.5) < 0.5
+
+
+# --------------------------------------------------------------------------
 # Flow: Laplace law for a bubble (Appendix A.1, Eq. A1, Fig. A1)
 # --------------------------------------------------------------------------
 @pytest.mark.slow
