@@ -118,7 +118,9 @@ static int validate(const orc_params* p, char* err, int errlen) {
       if (!(p->hom_Mgas[r] > 0.0) || !(p->hom_Keq[r] > 0.0)) return fail(err, errlen, "R1 needs M_gas > 0 and K_eq > 0");
     }
     if (!(p->hom_k[r] >= 0.0)) return fail(err, errlen, "rate constants must be >= 0");
+    if (p->hom_surface[r] && !(p->hom_sfac[r] > 0.0)) return fail(err, errlen, "surface factor must be > 0");
   }
+  if (!(p->psi_pre > 0.0)) return fail(err, errlen, "psi prefactor must be > 0");
   for (int r = 0; r < p->n_het; ++r) {
     if (p->het_reactant[r] < 0 || p->het_reactant[r] >= ns) return fail(err, errlen, "bad het reactant");
     if (p->het_product[r] < -1 || p->het_product[r] >= ns) return fail(err, errlen, "bad het product");
@@ -299,7 +301,7 @@ static int macros(orc_sim* s) {
    * (weights 1/3, 1/12, whose second moment is the identity) reproduce the
    * EOS of Eq. 12: p = rho/3 + G11 psi^2 / 2, so psi = sqrt(2 (p - rho/3)/G11).
    * The printed 6/G11 belongs to weights whose second moment is c_s^2 I; it is
-   * kept behind psi_literal.  A negative argument is clamped to zero and counted.
+   * selected by psi_pre = 6.  A negative argument is clamped to zero and counted.
    * phi_1(rho_2), phi_2(rho_1): Eq. 15 with the natural logarithm in rho_10. */
   for (int i = 0; i < N; ++i) {
     s->psi1[i] = s->phi1[i] = s->phi2[i] = 0.0;
@@ -311,7 +313,7 @@ static int macros(orc_sim* s) {
                  i % nx, i / nx, (long long)s->step);
         return -1;
       }
-      const double pre = p->psi_literal ? 6.0 : 2.0;
+      const double pre = p->psi_pre;
       double arg = pre * (p_cs(p, r1) - r1 / 3.0) / p->G11;
       if (arg < 0.0) {
         arg = 0.0;
@@ -436,18 +438,27 @@ int orc_step(orc_sim* s, int nsteps) {
       s->Ss[i] = s->Ss[N + i] = 0.0;
       for (int k = 0; k < ns; ++k) s->Sk[k * N + i] = 0.0;
       if (!s->liq[i]) continue;
+      /* types of the D2Q5 neighbours inside the domain: a reaction with a
+       * surface mask runs k * factor next to those solids (Sec. 2: R1 is
+       * 1000 times faster at the D(s) surface than in the bulk) */
+      int nbt = 0;
+      for (int a = 1; a < 5; ++a) {
+        const int j = nb(s, i % nx, i / nx, a);
+        if (j >= 0) nbt |= 1 << s->type[j];
+      }
       for (int r = 0; r < p->n_hom; ++r) {
         const int re0 = p->hom_re[r][0], re1 = p->hom_re[r][1];
         const int pr0 = p->hom_pr[r][0], pr1 = p->hom_pr[r][1];
+        const double kr = (p->hom_surface[r] & nbt) ? p->hom_k[r] * p->hom_sfac[r] : p->hom_k[r];
         double R = 0.0;
         if (p->hom_kind[r] == ORC_HOM_FIRST_ORDER) {
-          R = p->hom_k[r] * s->C[re0 * N + i];
+          R = kr * s->C[re0 * N + i];
         } else if (p->hom_kind[r] == ORC_HOM_BIMOLECULAR) {
-          R = p->hom_k[r] * s->C[re0 * N + i] * s->C[re1 * N + i];
+          R = kr * s->C[re0 * N + i] * s->C[re1 * N + i];
         } else {
           double cg = s->rho[N + i] / p->hom_Mgas[r];
           if (cg < 0.0) cg = 0.0;
-          R = p->hom_k[r] * (s->C[re0 * N + i] - s->C[pr0 * N + i] * sqrt(cg) / p->hom_Keq[r]);
+          R = kr * (s->C[re0 * N + i] - s->C[pr0 * N + i] * sqrt(cg) / p->hom_Keq[r]);
           /* Eq. 27: half a mole of gas per mole of R1, moved from the liquid to the gas component */
           s->Ss[i] -= 0.5 * R * p->hom_Mgas[r];
           s->Ss[N + i] += 0.5 * R * p->hom_Mgas[r];

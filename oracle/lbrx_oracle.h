@@ -46,7 +46,8 @@ typedef struct {
   double G11, G12, G21;   /* interaction strengths (Eq. 11, 14) */
   double a0, rho10, rho20;/* inter-component effective masses (Eq. 15) */
   double liquid_frac;     /* liquid iff rho1 > liquid_frac * max rho1 (Sec. 4.5) */
-  int32_t psi_literal;    /* 1: use the printed 6/G11 prefactor of Eq. 13 (diagnostic) */
+  double psi_pre;         /* psi = sqrt(psi_pre (p - rho/3) / G11): 2 reproduces Eq. 12 with
+                             the weights of Eq. 11; 6 is the printed prefactor of Eq. 13 */
   int32_t n_species;
   double tau_g[ORC_MAX_SPECIES];
   double J0[ORC_MAX_SPECIES];
@@ -57,6 +58,8 @@ typedef struct {
   double hom_k[ORC_MAX_RXN];
   double hom_Keq[ORC_MAX_RXN];
   double hom_Mgas[ORC_MAX_RXN];
+  int32_t hom_surface[ORC_MAX_RXN];  /* bit (1<<type): solid types whose D2Q5 adjacency enhances k */
+  double hom_sfac[ORC_MAX_RXN];      /* factor on k next to such a solid (R1 at D(s), Sec. 2) */
   int32_t n_het;
   int32_t het_reactant[ORC_MAX_RXN];
   int32_t het_product[ORC_MAX_RXN];

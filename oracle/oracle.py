@@ -28,11 +28,12 @@ class _Params(C.Structure):
         ("a", C.c_double), ("b", C.c_double), ("R", C.c_double), ("T", C.c_double),
         ("G11", C.c_double), ("G12", C.c_double), ("G21", C.c_double),
         ("a0", C.c_double), ("rho10", C.c_double), ("rho20", C.c_double),
-        ("liquid_frac", C.c_double), ("psi_literal", C.c_int32),
+        ("liquid_frac", C.c_double), ("psi_pre", C.c_double),
         ("n_species", C.c_int32), ("tau_g", C.c_double * MAXS), ("J0", C.c_double * MAXS),
         ("n_hom", C.c_int32), ("hom_kind", C.c_int32 * MAXR),
         ("hom_re", (C.c_int32 * 2) * MAXR), ("hom_pr", (C.c_int32 * 2) * MAXR),
         ("hom_k", C.c_double * MAXR), ("hom_Keq", C.c_double * MAXR), ("hom_Mgas", C.c_double * MAXR),
+        ("hom_surface", C.c_int32 * MAXR), ("hom_sfac", C.c_double * MAXR),
         ("n_het", C.c_int32), ("het_reactant", C.c_int32 * MAXR), ("het_product", C.c_int32 * MAXR),
         ("het_surface", C.c_int32 * MAXR), ("het_mode", C.c_int32 * MAXR), ("het_irrev", C.c_int32 * MAXR),
         ("het_k", C.c_double * MAXR), ("het_Ceq", C.c_double * MAXR), ("het_mvol", C.c_double * MAXR),
@@ -102,7 +103,8 @@ def _params(prob, psi_literal=False):
     p.gbody[:] = list(prob.gbody)
     for k in ("a", "b", "R", "T", "G11", "G12", "G21", "a0", "rho10", "rho20", "liquid_frac"):
         setattr(p, k, float(getattr(prob, k)))
-    p.psi_literal = int(psi_literal)
+    # Eq. 13 as printed (6) when asked for, else the problem's prefactor (0: 2)
+    p.psi_pre = 6.0 if psi_literal else (float(prob.psi_prefactor) or 2.0)
     if prob.n_species > MAXS or len(prob.hom) > MAXR or len(prob.het) > MAXR:
         raise ValueError("too many species or reactions")
     p.n_species = prob.n_species
@@ -115,6 +117,8 @@ def _params(prob, psi_literal=False):
         p.hom_re[i][0], p.hom_re[i][1] = r.re
         p.hom_pr[i][0], p.hom_pr[i][1] = r.pr
         p.hom_k[i], p.hom_Keq[i], p.hom_Mgas[i] = r.k, r.K_eq, r.M_gas
+        p.hom_surface[i] = sum(1 << t for t in r.surface)
+        p.hom_sfac[i] = r.surface_factor
     p.n_het = len(prob.het)
     for i, r in enumerate(prob.het):
         p.het_reactant[i], p.het_product[i] = r.reactant, r.product

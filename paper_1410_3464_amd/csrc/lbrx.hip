@@ -125,6 +125,8 @@ struct KConst {
   int nhom;
   int hkind[LBRX_MAX_RXN], hre0[LBRX_MAX_RXN], hre1[LBRX_MAX_RXN], hpr0[LBRX_MAX_RXN], hpr1[LBRX_MAX_RXN];
   double hk[LBRX_MAX_RXN], hKeq[LBRX_MAX_RXN], hMgas[LBRX_MAX_RXN];
+  int hsurf[LBRX_MAX_RXN], any_hsurf;  // surface-enhanced rates: solid-type bits, any at all
+  double hks[LBRX_MAX_RXN];            // rate constant times the surface factor
   int nhet;
   int xre[LBRX_MAX_RXN], xpr[LBRX_MAX_RXN], xsurf[LBRX_MAX_RXN], xmode[LBRX_MAX_RXN], xirrev[LBRX_MAX_RXN];
   double xkap[LBRX_MAX_RXN], xCeq[LBRX_MAX_RXN], xmvol[LBRX_MAX_RXN];
@@ -137,7 +139,8 @@ template <typename T> struct KT {
       rho20, r_rho20;
   T J[LBRX_MAX_SPECIES][5];
   T omg[LBRX_MAX_SPECIES];
-  T hk[LBRX_MAX_RXN], hKeq[LBRX_MAX_RXN], r_hKeq[LBRX_MAX_RXN], hMgas[LBRX_MAX_RXN], r_hMgas[LBRX_MAX_RXN];
+  T hk[LBRX_MAX_RXN], hks[LBRX_MAX_RXN], hKeq[LBRX_MAX_RXN], r_hKeq[LBRX_MAX_RXN], hMgas[LBRX_MAX_RXN],
+      r_hMgas[LBRX_MAX_RXN];
   T xkap[LBRX_MAX_RXN], xCeq[LBRX_MAX_RXN];
   T hnu[LBRX_MAX_RXN][LBRX_MAX_SPECIES];  // net stoichiometric coefficient of species k in reaction r
   // 16-bit storage: deviation scales (powers of two) and reference-code bases
@@ -898,17 +901,27 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
           for (int kk = 0; kk < NSA; ++kk) Sk[kk] = T(0);
           T Ss[2] = {T(0), T(0)};
           if (liq) {
+            // solid types among the D2Q5 neighbours (surface-enhanced rates)
+            uint32_t nbt = 0u;
+            if (c.any_hsurf) {
+#pragma unroll
+              for (int a = 1; a < 5; ++a)
+                if (!(nt[a] & TB_WALL)) nbt |= 1u << (nt[a] & TB_T);
+            }
             for (int r = 0; r < c.nhom; ++r) {
               T Rr;
+              // (behind the uniform test, the rate stays a scalar operand)
+              T kr = k.hk[r];
+              if (c.any_hsurf && (c.hsurf[r] & nbt)) kr = k.hks[r];
               if (c.hkind[r] == HOM_FIRST) {
-                Rr = k.hk[r] * sel<NS>(m.C, c.hre0[r]);
+                Rr = kr * sel<NS>(m.C, c.hre0[r]);
               } else if (c.hkind[r] == HOM_BI) {
-                Rr = k.hk[r] * sel<NS>(m.C, c.hre0[r]) * sel<NS>(m.C, c.hre1[r]);
+                Rr = kr * sel<NS>(m.C, c.hre0[r]) * sel<NS>(m.C, c.hre1[r]);
               } else {
                 T cg = cdiv<T>(r2, k.hMgas[r], k.r_hMgas[r]);
                 if (cg < T(0)) cg = T(0);
-                Rr = k.hk[r] * (sel<NS>(m.C, c.hre0[r]) -
-                                cdiv<T>(sel<NS>(m.C, c.hpr0[r]) * dsqrt<T>(cg), k.hKeq[r], k.r_hKeq[r]));
+                Rr = kr * (sel<NS>(m.C, c.hre0[r]) -
+                           cdiv<T>(sel<NS>(m.C, c.hpr0[r]) * dsqrt<T>(cg), k.hKeq[r], k.r_hKeq[r]));
                 Ss[0] -= T(0.5) * Rr * k.hMgas[r];
                 Ss[1] += T(0.5) * Rr * k.hMgas[r];
               }
@@ -1491,7 +1504,12 @@ std::string validate(const lbrx_params* p) {
     if (h.kind == LBRX_HOM_R1_GAS && (h.pr[0] < 0 || !(h.M_gas > 0.0) || !(h.K_eq > 0.0)))
       return "R1 reaction needs an aqueous product, M_gas > 0 and K_eq > 0";
     if (!(h.k >= 0.0)) return "rate constants must be >= 0";
+    if (h.surface & ~((1u << LBRX_SOLID_INERT) | (1u << LBRX_SOLID_D) | (1u << LBRX_SOLID_F)))
+      return "a homogeneous reaction's surface may only name solid types";
+    if (h.surface && !(h.surface_factor > 0.0 && h.surface_factor < 1e300))
+      return "surface_factor must be positive and finite";
   }
+  if (!(p->psi_prefactor >= 0.0 && p->psi_prefactor < 1e300)) return "psi_prefactor must be 0 (default) or positive";
   for (int r = 0; r < p->n_het; ++r) {
     const lbrx_het_rxn& h = p->het[r];
     if (h.reactant < 0 || h.reactant >= ns || h.product < -1 || h.product >= ns) return "species index out of range";
@@ -1747,6 +1765,7 @@ void fill_kt(KT<T>& k, const lbrx_params* p, const KConst& c, const double* D) {
   }
   for (int r = 0; r < LBRX_MAX_RXN; ++r) {
     k.hk[r] = (T)c.hk[r];
+    k.hks[r] = (T)c.hks[r];
     k.hKeq[r] = (T)c.hKeq[r];
     k.r_hKeq[r] = (T)(c.hKeq[r] != 0.0 ? 1.0 / c.hKeq[r] : 0.0);
     k.hMgas[r] = (T)c.hMgas[r];
@@ -1829,7 +1848,7 @@ lbrx_status lbrx_create(const lbrx_params* p, void* hip_stream, lbrx_ctx** out) 
   c.a = p->a;
   c.b = p->b;
   c.G11 = p->G11;
-  c.psi_pre = 2.0;
+  c.psi_pre = p->psi_prefactor > 0.0 ? p->psi_prefactor : 2.0;
   c.G12 = p->G12;
   c.G21 = p->G21;
   c.w1 = p->w_adh[0];
@@ -1860,6 +1879,9 @@ lbrx_status lbrx_create(const lbrx_params* p, void* hip_stream, lbrx_ctx** out) 
     c.hk[r] = p->hom[r].k;
     c.hKeq[r] = p->hom[r].K_eq;
     c.hMgas[r] = p->hom[r].M_gas;
+    c.hsurf[r] = (int)p->hom[r].surface;
+    c.hks[r] = p->hom[r].surface ? p->hom[r].k * p->hom[r].surface_factor : p->hom[r].k;
+    c.any_hsurf |= c.hsurf[r] != 0;
   }
   c.nhet = p->n_het;
   for (int r = 0; r < p->n_het; ++r) {

@@ -14,7 +14,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbrx.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 MAXS = 8
 MAXR = 8
 F64, F32, F16DEV, BF16DEV = 0, 1, 2, 3
@@ -33,7 +33,8 @@ SYMBOLS = ("lbrx_create", "lbrx_create_error", "lbrx_step", "lbrx_sync", "lbrx_f
 
 class HomRxn(C.Structure):
     _fields_ = [("kind", C.c_int32), ("re", C.c_int32 * 2), ("pr", C.c_int32 * 2),
-                ("k", C.c_double), ("K_eq", C.c_double), ("M_gas", C.c_double)]
+                ("k", C.c_double), ("K_eq", C.c_double), ("M_gas", C.c_double),
+                ("surface", C.c_uint32), ("surface_factor", C.c_double)]
 
 
 class HetRxn(C.Structure):
@@ -55,7 +56,7 @@ class Params(C.Structure):
         ("n_hom", C.c_int32), ("hom", HomRxn * MAXR),
         ("n_het", C.c_int32), ("het", HetRxn * MAXR),
         ("node_type", C.c_void_p), ("V0", C.c_void_p), ("rho1", C.c_void_p), ("rho2", C.c_void_p),
-        ("C0", C.c_void_p), ("seg_rows", C.c_int32),
+        ("C0", C.c_void_p), ("seg_rows", C.c_int32), ("psi_prefactor", C.c_double),
     ]
 
 
@@ -146,6 +147,9 @@ def make_params(prob, precision="f64", seg_rows=0):
         h.re[0], h.re[1] = r.re
         h.pr[0], h.pr[1] = r.pr
         h.k, h.K_eq, h.M_gas = r.k, r.K_eq, r.M_gas
+        h.surface = sum(1 << t for t in r.surface)
+        h.surface_factor = r.surface_factor
+    p.psi_prefactor = float(prob.psi_prefactor)
     p.n_het = len(prob.het)
     for i, r in enumerate(prob.het):
         h = p.het[i]

@@ -51,6 +51,9 @@ class HomRxn:
     kind: "first_order" (R = k C_re0), "r1_gas" (R = k (C_re0 - C_pr0 sqrt(rho2/M_gas)/K_eq),
     with half a mole of gas per mole moved from the liquid to the gas component),
     "bimolecular" (R = k C_re0 C_re1).  Indices refer to the species list; -1 = none.
+    surface, surface_factor: at a liquid node with a D2Q5 neighbour of one of the
+    solid types in `surface`, k is multiplied by surface_factor (the paper's R1 is
+    1000 times faster at the D(s) surface).
     """
 
     kind: str
@@ -59,6 +62,8 @@ class HomRxn:
     k: float = 0.0
     K_eq: float = 1.0
     M_gas: float = 1.0
+    surface: tuple = ()
+    surface_factor: float = 1.0
 
 
 @dataclass
@@ -101,6 +106,7 @@ class Problem:
     rho10: float = 0.0
     rho20: float = 0.003
     liquid_frac: float = 0.5
+    psi_prefactor: float = 0.0  # 0: 2 (weights of Eq. 11 reproduce Eq. 12); 6: as printed in Eq. 13
     species: list = field(default_factory=list)
     hom: list = field(default_factory=list)
     het: list = field(default_factory=list)

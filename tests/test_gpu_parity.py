@@ -5,6 +5,7 @@ event counts identical.  FP32: fields within 1e-5 after the stated steps.
 A mask may only differ after the oracle has had a threshold decision within
 the tolerance; those cases are reported and the masks are then not compared.
 """
+import dataclasses
 import math
 import os
 import sys
@@ -110,6 +111,37 @@ def test_fp64_parity_events():
     o.step(300)
     L = o.fields()["ledger"]
     assert L["n_dissolved"] > 0 and L["n_precipitated"] > 0
+
+
+def test_fp64_parity_surface_enhanced_rate():
+    """The porous medium with its R1-type reaction run 1000 times faster next
+    to D(s) (Sec. 2), the bulk rate lowered to 1e-4 so that the surface rate
+    stays below one per step: FP64 parity with the oracle."""
+    _, porous = _small_cases()
+    hom = [dataclasses.replace(r) for r in porous.hom]
+    hom[0] = dataclasses.replace(hom[0], k=1e-4, surface=(W.SOLID_D,), surface_factor=1000.0)
+    prob = porous.copy(hom=hom, name="porous-surface-rate")
+    _run_pair(prob, "f64", [1, 50, 300], 1e-12)
+
+
+def test_fp64_parity_literal_psi_prefactor():
+    """The effective mass with the prefactor printed in Eq. 13 (6 instead of
+    2): a supercritical two-component fluid driven past an inert disk by a
+    body force (a sharper state diverges with that prefactor; without the
+    flow the velocities are a 1e-4 residual of cancelling forces and a
+    relative norm magnifies rounding); FP64 parity with the oracle."""
+    a, b, R = W.EOS_ORIGINAL
+    nx, ny = 70, 45
+    rng = np.random.default_rng(3)
+    rho1 = 0.2 * (1 + 0.02 * rng.uniform(-1, 1, (ny, nx)))
+    rho2 = 0.1 * (1 + 0.02 * rng.uniform(-1, 1, (ny, nx)))
+    yy, xx = np.mgrid[:ny, :nx]
+    t = np.where((xx - 20) ** 2 + (yy - 22) ** 2 <= 36, W.SOLID_INERT, W.FLUID).astype(np.uint8)
+    p = W.uniform_problem(nx, ny, ideal=False, a=a, b=b, R=R, T=2.0 * W.critical_temperature(a, b, R),
+                          G11=-1.0, G12=0.5, G21=0.5, rho10=W.paper_rho10(), rho20=0.003, a0=0.005,
+                          rho1=1.0, psi_prefactor=6.0, gbody=(1e-5, 0.0))
+    prob = p.copy(rho1=rho1, rho2=rho2, type0=t, V0=np.where(t > 0, 1.0, 0.0), name="literal-psi")
+    _run_pair(prob, "f64", [1, 50, 300], 1e-12)
 
 
 def test_fp32_parity_droplet():

@@ -249,6 +249,33 @@ def test_first_order_decay_closed_form():
     assert np.allclose(F["C"][0] + F["C"][1], 0.7, rtol=1e-13, atol=0)
 
 
+@pytest.mark.parametrize("surface,enhanced", [((W.SOLID_D,), True), ((W.SOLID_F,), False)])
+def test_surface_enhanced_rate_closed_form(surface, enhanced):
+    """A two-row liquid channel between rows of dissolvable solid (no surface
+    reactions): every liquid node has a D(s) neighbour, so a first-order A -> B
+    whose rate is multiplied at the D(s) surface (Sec. 2: R1 is 1000 times
+    faster there) decays as C_A(n) = C_A(0) (1 - k f)^n; a factor tied to
+    another solid type leaves the bulk rate k."""
+    k, f, n = 1e-5, 1000.0, 200
+    nx, ny = 6, 4
+    sp = [W.Species("A"), W.Species("B")]
+    C0 = np.zeros((2, ny, nx))
+    C0[0] = 0.6
+    t = np.zeros((ny, nx), np.uint8)
+    t[0] = t[-1] = W.SOLID_D
+    p = W.uniform_problem(nx, ny, rho1=1.0, species=sp, C0=C0,
+                          hom=[W.HomRxn("first_order", re=(0, -1), pr=(1, -1), k=k,
+                                        surface=surface, surface_factor=f)])
+    p = p.copy(type0=t, V0=np.where(t > 0, 1.0, 0.0))
+    s = OracleSim(p)
+    s.step(n)
+    F = s.fields()
+    keff = k * f if enhanced else k
+    live = F["C"][0][1:-1]
+    assert np.allclose(live, 0.6 * (1 - keff) ** n, rtol=1e-12, atol=0)
+    assert np.allclose(F["C"][0][1:-1] + F["C"][1][1:-1], 0.6, rtol=1e-13, atol=0)
+
+
 def test_bimolecular_invariants():
     """Uniform B + E -> F (Eq. 5c, 28): B - E and B + F, E + F are conserved and
     the decay follows the second-order law within the explicit scheme's O(k dt) error."""
