@@ -117,6 +117,7 @@ struct KConst {
   int nx, ny, pitch, per_x, per_y, strips, seg_rows, nitems, nblocks, ns;
   unsigned fbytes, gbytes, tbytes, cbytes;  // array sizes (buffer ranges)
   int ncw;                                  // solute code words per node (16-bit storage)
+  int sg;                                   // species per solute slot (species_group)
   long long plane;
   double om[2], tau[2], RT, a, b, G11, psi_pre, G12, G21, w1, w2, gx, gy, a0, rho10, rho20, lfrac;
   int has_psi, has_phi1, has_phi2;
@@ -408,6 +409,46 @@ template <typename ST> __device__ inline void bstore2(ST lo, ST hi, __amdgpu_buf
   }
 }
 
+// Species per solute slot: the four species of a group share one slot of a
+// direction (16 bytes in FP32, 8 in 16-bit storage) when the species count is
+// a multiple of four, else pairs (FP64 always: 16 bytes).  A wider slot puts
+// fewer nodes in a 128-byte line, so fewer lines are only partly used where
+// liquid meets gas or solid, and one load or store moves the whole group.
+__host__ __device__ constexpr int species_group(int ns, int esz) { return (ns > 0 && ns % 4 == 0 && esz <= 4) ? 4 : 2; }
+
+template <typename ST, int SG> struct Grp {
+  ST v[SG];
+};
+template <typename ST, int SG> __device__ inline Grp<ST, SG> bloadg(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+  Grp<ST, SG> g;
+  if constexpr (SG == 2) {
+    const Pair<ST> q = bload2<ST>(r, vo, so);
+    g.v[0] = q.lo;
+    g.v[1] = q.hi;
+  } else {
+    // reinterpreted as a whole vector of ST, as for pairs
+    typedef ST vs_t __attribute__((ext_vector_type(SG)));
+    vs_t u;
+    if constexpr (sizeof(ST) * SG == 8) u = __builtin_bit_cast(vs_t, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0));
+    else u = __builtin_bit_cast(vs_t, __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, 0));
+#pragma unroll
+    for (int i = 0; i < SG; ++i) g.v[i] = u[i];
+  }
+  return g;
+}
+template <typename ST, int SG> __device__ inline void bstoreg(const Grp<ST, SG>& g, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+  if constexpr (SG == 2) {
+    bstore2<ST>(g.v[0], g.v[1], r, vo, so);
+  } else {
+    typedef ST vs_t __attribute__((ext_vector_type(SG)));
+    vs_t u;
+#pragma unroll
+    for (int i = 0; i < SG; ++i) u[i] = g.v[i];
+    if constexpr (sizeof(ST) * SG == 8) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u_t, u), r, (int)vo, (int)so, STORE_NT);
+    else __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4u_t, u), r, (int)vo, (int)so, STORE_NT);
+  }
+}
+
 template <typename T, int NS> struct Mom {
   T rho[2], jx[2], jy[2], C[NS > 0 ? NS : 1];
 };
@@ -471,11 +512,15 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
   const int nrow = y1 - y0;
   const int nx = c.nx, ny = c.ny;
   const unsigned upitch = (unsigned)c.pitch;
-  constexpr int NSP = (NS + 1) / 2;    // species pairs
-  constexpr unsigned PE = 2 * ES;      // bytes per slot (a pair)
-  const unsigned PS = upitch * PE;     // bytes per slot plane row
+  constexpr unsigned PE = 2 * ES;      // bytes per flow slot (a pair)
+  const unsigned PS = upitch * PE;     // bytes per flow slot plane row
   const unsigned RSF = 9u * PS;        // bytes per lattice row, flow: 9 directions x (component 1, 2)
-  const unsigned RSG = 5u * NSP * PS;  // bytes per lattice row, solute: species pairs x 5 directions
+  constexpr int SG = species_group(NS, (int)ES);  // species per solute slot
+  constexpr int NGR = (NS + SG - 1) / SG;         // species groups
+  constexpr unsigned PEG = SG * ES;               // bytes per solute slot
+  constexpr int GSH = SG == 4 ? 1 : 0;            // PEG = PE << GSH
+  const unsigned PSG = upitch * PEG;              // bytes per solute slot plane row
+  const unsigned RSG = 5u * NGR * PSG;            // bytes per lattice row, solute: groups x 5 directions
 
   const __amdgpu_buffer_rsrc_t rf = rsrc_of(A.f[cur], c.fbytes);
   const __amdgpu_buffer_rsrc_t rg = rsrc_of(A.g[cur], c.gbytes);
@@ -552,7 +597,7 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
       }
     }
     if (NS > 0 && liqp) {
-      const unsigned own = co[1] + ur[1] * RSG;
+      const unsigned own = (co[1] << GSH) + ur[1] * RSG;
       T gb[NSA][2];
       if constexpr (DEV) {
         // this node's solute reference codes, one word per four species
@@ -570,13 +615,14 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
         if constexpr (DEV) return __builtin_fmaf(dev_in<SM>(v), k.iscg[kk], gb[kk][a == 0 ? 0 : 1]);
         else return v;
       };
-      // species pair j holds species 2j (low) and 2j + 1 (high)
+      // species group j holds species SG j .. SG j + SG - 1
       auto gin = [&](int a, unsigned vo) {
 #pragma unroll
-        for (int j = 0; j < NSP; ++j) {
-          const Pair<ST> q = bload2<ST>(rg, vo, (unsigned)(j * 5) * PS);
-          g[2 * j][a] = gcv(2 * j, a, q.lo);
-          if (2 * j + 1 < NS) g[2 * j + 1][a] = gcv(2 * j + 1, a, q.hi);
+        for (int j = 0; j < NGR; ++j) {
+          const Grp<ST, SG> q = bloadg<ST, SG>(rg, vo, (unsigned)(j * 5) * PSG);
+#pragma unroll
+          for (int i = 0; i < SG; ++i)
+            if (j * SG + i < NS) g[j * SG + i][a] = gcv(j * SG + i, a, q.v[i]);
         }
       };
       gin(0, own);
@@ -584,7 +630,7 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
       for (int b = 1; b < 5; ++b) {
         const int a = opp(b);
         const bool src = (w >> (NBL_SHIFT + b - 1)) & 1u;
-        gin(a, src ? co[ex(b) + 1] + (ur[ey(b) + 1] * RSG + (unsigned)a * PS) : own + (unsigned)b * PS);
+        gin(a, src ? (co[ex(b) + 1] << GSH) + (ur[ey(b) + 1] * RSG + (unsigned)a * PSG) : own + (unsigned)b * PSG);
       }
     }
   };
@@ -1233,13 +1279,16 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
         bstore<uint32_t>(wout, wt_, (unsigned)X * 4u, (unsigned)R * upitch * 4u);
         const unsigned long long bf = __ballot(storef);
         const unsigned long long bg = __ballot(storeg);
-        // a 128-byte line holds the slots of 128 / PE lanes (32 for 16-bit
-        // pairs, 16 for FP32, 8 for FP64); the solute code words, 32 lanes
+        // a 128-byte line holds the flow slots of 128 / PE lanes (32 for
+        // 16-bit pairs, 16 for FP32, 8 for FP64), the solute slots of
+        // 128 / PEG lanes; the solute code words, 32 lanes
         constexpr int G = 128 / PE;
         constexpr unsigned long long GM = (1ull << G) - 1ull;
         const int gl = lane & ~(G - 1);
         const bool gf = ((bf >> gl) & GM) != 0ull;
-        const bool gg = ((bg >> gl) & GM) != 0ull;
+        constexpr int GG = 128 / PEG;
+        constexpr unsigned long long GGM = (1ull << GG) - 1ull;
+        const bool gg = ((bg >> (lane & ~(GG - 1))) & GGM) != 0ull;
         const bool gw = ((bg >> (lane & 32)) & 0xffffffffull) != 0ull;
         const unsigned xo = (unsigned)X * PE;
         if (gf) {
@@ -1270,7 +1319,7 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
           }
         }
         if (NS > 0 && gg) {
-          const unsigned vo = xo + (unsigned)R * RSG;
+          const unsigned vo = (xo << GSH) + (unsigned)R * RSG;
           if constexpr (DEV) {
             // deviation from J_a x the reference concentration of the reader:
             // the liquid neighbour it heads to, else this node
@@ -1280,18 +1329,21 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
 #pragma unroll
             for (int a = 0; a < 5; ++a) {
               const bool nbr = a != 0 && is_liq(nt[a]);
-              uint16_t hv[2 * NSP > 0 ? 2 * NSP : 1];
 #pragma unroll
-              for (int kk = 0; kk < 2 * NSP; ++kk) {
-                if (kk < NS) {
-                  const T cr = nbr ? L.Cf[kk][slot(ey(a))][lane + 1 + ex(a)] : co_[kk];
-                  hv[kk] = dev_out<SM>(__builtin_fmaf(g[kk][a], k.scg[kk], -(k.Jsc[kk][a == 0 ? 0 : 1] * cr)));
-                } else {
-                  hv[kk] = 0;
+              for (int j = 0; j < NGR; ++j) {
+                Grp<ST, SG> hv;
+#pragma unroll
+                for (int i = 0; i < SG; ++i) {
+                  const int kk = j * SG + i;
+                  if (kk < NS) {
+                    const T cr = nbr ? L.Cf[kk][slot(ey(a))][lane + 1 + ex(a)] : co_[kk];
+                    hv.v[i] = dev_out<SM>(__builtin_fmaf(g[kk][a], k.scg[kk], -(k.Jsc[kk][a == 0 ? 0 : 1] * cr)));
+                  } else {
+                    hv.v[i] = 0;
+                  }
                 }
+                bstoreg<ST, SG>(hv, wg_, vo, (unsigned)(j * 5 + a) * PSG);
               }
-#pragma unroll
-              for (int j = 0; j < NSP; ++j) bstore2<ST>(hv[2 * j], hv[2 * j + 1], wg_, vo, (unsigned)(j * 5 + a) * PS);
             }
             // the node's solute reference codes, for its own pull next step
             const __amdgpu_buffer_rsrc_t wc_ = rsrc_of(A.cw[1 - cur], c.cbytes);
@@ -1309,10 +1361,14 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
             }
           } else {
 #pragma unroll
-            for (int j = 0; j < NSP; ++j)
+            for (int j = 0; j < NGR; ++j)
 #pragma unroll
-              for (int a = 0; a < 5; ++a)
-                bstore2<ST>(g[2 * j][a], 2 * j + 1 < NS ? g[2 * j + 1][a] : T(0), wg_, vo, (unsigned)(j * 5 + a) * PS);
+              for (int a = 0; a < 5; ++a) {
+                Grp<ST, SG> q;
+#pragma unroll
+                for (int i = 0; i < SG; ++i) q.v[i] = j * SG + i < NS ? g[j * SG + i][a] : T(0);
+                bstoreg<ST, SG>(q, wg_, vo, (unsigned)(j * 5 + a) * PSG);
+              }
           }
         }
       }
@@ -1522,9 +1578,11 @@ std::string validate(const lbrx_params* p) {
     // the kernels address each population array with 32-bit byte offsets
     const unsigned long long pitch = ((unsigned long long)p->nx + 63) / 64 * 64;
     const unsigned long long esz = storage_bytes(p->precision);
-    // slots of pairs: 9 flow planes, 5 planes per pair of species
-    const unsigned long long np = 9ull > 5ull * ((p->n_species + 1) / 2) ? 9ull : 5ull * ((p->n_species + 1) / 2);
-    if (np * pitch * (unsigned long long)p->ny * 2ull * esz >= (1ull << 32))
+    // elements per node: 9 flow pairs; 5 slots per species group
+    const unsigned long long sg = (unsigned long long)species_group(p->n_species, (int)esz);
+    const unsigned long long ge = 5ull * ((p->n_species + sg - 1) / sg) * sg;
+    const unsigned long long np = 18ull > ge ? 18ull : ge;
+    if (np * pitch * (unsigned long long)p->ny * esz >= (1ull << 32))
       return "lattice too large: a population array must stay below 4 GiB (use FP32 or fewer species)";
   }
   if (ns > 0 && !p->C0) return "C0 is required when n_species > 0";
@@ -1542,18 +1600,19 @@ std::string validate(const lbrx_params* p) {
   return "";
 }
 
-// Element index of the slot layout: row-interleaved planes of pairs.  Flow:
+// Element index of the slot layout: row-interleaved planes of slots.  Flow:
 // plane a of row y holds (component 1, component 2) of direction a; solute:
-// plane 5j + a holds (species 2j, species 2j + 1) of direction a.
+// plane 5j + a holds species sg j .. sg j + sg - 1 of direction a (sg from
+// species_group: 4 or 2).
 inline long long fslot(const KConst& c, int y, int a, int x, int s) {
   return (((long long)y * 9 + a) * c.pitch + x) * 2 + s;
 }
+inline int n_groups(const KConst& c) { return (c.ns + c.sg - 1) / c.sg; }
 inline long long gslot(const KConst& c, int y, int k, int a, int x) {
-  const int nsp = (c.ns + 1) / 2;
-  return (((long long)y * 5 * nsp + (k >> 1) * 5 + a) * c.pitch + x) * 2 + (k & 1);
+  return (((long long)y * 5 * n_groups(c) + (k / c.sg) * 5 + a) * c.pitch + x) * c.sg + (k % c.sg);
 }
 size_t f_elems(const KConst& c) { return (size_t)18 * c.plane; }
-size_t g_elems(const KConst& c) { return (size_t)10 * ((c.ns + 1) / 2) * c.plane + 2; }
+size_t g_elems(const KConst& c) { return (size_t)5 * n_groups(c) * c.sg * c.plane + c.sg; }
 
 template <typename T>
 void fill_populations(const lbrx_params* p, const KConst& c, const std::vector<uint32_t>& tb,
@@ -1825,6 +1884,7 @@ lbrx_status lbrx_create(const lbrx_params* p, void* hip_stream, lbrx_ctx** out) 
   c.ns = p->n_species;
   x->precision = p->precision;
   x->esz = storage_bytes(p->precision);
+  c.sg = species_group(c.ns, (int)x->esz);
   c.seg_rows = p->seg_rows > 0 ? p->seg_rows : SEG_ROWS;
   if (const char* e = getenv("LBRX_SEG_ROWS")) {
     const int v = atoi(e);
