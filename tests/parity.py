@@ -7,6 +7,8 @@ Rules:
   within the tolerance of a threshold that decides them (then the first
   step where that happens is reported and the comparison of masks stops).
 """
+import dataclasses
+
 import numpy as np
 
 FIELDS = ("rho1", "rho2", "ux", "uy", "V")
@@ -60,3 +62,28 @@ def ledger_errors(LG, LO, ns):
     for k in ("n_psi_clamp", "n_dissolved", "n_precipitated", "n_liq_to_gas", "n_gas_to_liq", "steps"):
         out[k] = abs(LG[k] - LO[k])
     return out
+
+
+def species_variant(prob, ns):
+    """The porous problem with `ns` species: the first min(ns, 4) as given
+    (reactions that name a dropped species are dropped), the others copies of
+    species 0-3 shifted by 4 with their own initial concentration and
+    reactions, so that every species slot carries distinct values."""
+    sp, C0 = [], np.zeros((ns,) + prob.C0.shape[1:])
+    for q in range(ns):
+        sp.append(dataclasses.replace(prob.species[q % 4], name=f"S{q}", tau_g=0.8 + 0.05 * q))
+        C0[q] = prob.C0[q % 4] * (1.0 + 0.1 * (q // 4)) + 0.05 * q
+    def ok(idx):
+        return all(i < ns for i in idx if i >= 0)
+    hom, het = [], []
+    for off in range(0, ns, 4):
+        for r in prob.hom:
+            re_ = tuple(i + off if i >= 0 else -1 for i in r.re)
+            pr_ = tuple(i + off if i >= 0 else -1 for i in r.pr)
+            if ok(re_ + pr_):
+                hom.append(dataclasses.replace(r, re=re_, pr=pr_))
+        for r in prob.het:
+            rp = r.product + off if r.product >= 0 else -1
+            if ok((r.reactant + off, rp)):
+                het.append(dataclasses.replace(r, reactant=r.reactant + off, product=rp))
+    return prob.copy(species=sp, C0=C0, hom=hom[:8], het=het[:8], name=f"{prob.name}-ns{ns}")

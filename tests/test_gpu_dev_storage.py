@@ -23,7 +23,7 @@ from paper_1410_3464_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 sys.path.insert(0, os.path.dirname(__file__))
-from parity import compare  # noqa: E402
+from parity import compare, species_variant  # noqa: E402
 
 HALF_ULP = {"f16dev": 2.0 ** -11, "bf16dev": 2.0 ** -8}
 
@@ -34,11 +34,19 @@ def _lbrx():
     return Lbrx
 
 
+@pytest.mark.parametrize("case", ["droplet-ns2", "porous-ns4", "porous-ns8"])
 @pytest.mark.parametrize("precision", ["f16dev", "bf16dev"])
-def test_initial_state_reads_back(precision):
+def test_initial_state_reads_back(precision, case):
     """Step 0 exported from 16-bit storage: densities and concentrations within
-    the encoding bound (every node reads its own slots at step 0)."""
-    p = W.config0()
+    the encoding bound (every node reads its own slots at step 0).  Two
+    species use pair slots; four and eight, one and two slots of four species
+    (eight also a second word of solute reference codes)."""
+    if case == "droplet-ns2":
+        p = W.config0()
+    else:
+        p = W.config1(nx=130, ny=70, seed=11)
+        if case == "porous-ns8":
+            p = species_variant(p, 8)
     g = _lbrx()(p, precision)
     G = g.fields()
     fl = p.type0 == 0

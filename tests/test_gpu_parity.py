@@ -19,7 +19,7 @@ from paper_1410_3464_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 sys.path.insert(0, os.path.dirname(__file__))
-from parity import compare, ledger_errors  # noqa: E402
+from parity import compare, ledger_errors, species_variant  # noqa: E402
 
 
 def _gpu():
@@ -142,6 +142,21 @@ def test_fp64_parity_literal_psi_prefactor():
                           rho1=1.0, psi_prefactor=6.0, gbody=(1e-5, 0.0))
     prob = p.copy(rho1=rho1, rho2=rho2, type0=t, V0=np.where(t > 0, 1.0, 0.0), name="literal-psi")
     _run_pair(prob, "f64", [1, 50, 300], 1e-12)
+
+
+@pytest.mark.parametrize("ns", [3, 8])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_parity_species_counts(ns, precision):
+    """Species counts that do not fill groups of four (3: pairs, one padded)
+    and that fill two (8: two groups of four in FP32, four pairs in FP64) on
+    the ragged porous medium: FP64 within 1e-12 over 300 steps, FP32 within
+    1e-5 over 10 steps."""
+    _, porous = _small_cases()
+    prob = species_variant(porous, ns)
+    if precision == "f64":
+        _run_pair(prob, "f64", [1, 50, 300], 1e-12)
+    else:
+        _run_pair(prob, "f32", [1, 10], 1e-5)
 
 
 def test_fp32_parity_droplet():
