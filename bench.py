@@ -26,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+FILL_NODES = 4_000_000  # batched item heights are tuned on copies holding about this many nodes
 METRIC = "coupled-step MLUPS & %HBM roofline on 1 MI355X; serving p50/p99 vs plain"
 
 
@@ -105,8 +106,8 @@ def batched(n_inst, steps, warmup=30, plain_warmup=5):
     """Many independent simulations: n_inst FP32 instances of the porous-medium
     generator (square sides log-uniform in 64-1024, porosity uniform in
     0.4-0.8, rate constants log-uniform in 1e-6-1e-1), advanced together by one
-    launch per step (HIP graphs of 30 steps; item heights from the autotuner),
-    against the same instances run one after the other, each alone with the
+    launch per step (HIP graphs of 30 steps; item heights from the autotuner,
+    timed on batches of copies that fill the device), against the same instances run one after the other, each alone with the
     default item height.  Both sides time `steps` steps per instance after
     warm-up steps; creating the simulations is outside the timed regions."""
     import torch
@@ -118,7 +119,7 @@ def batched(n_inst, steps, warmup=30, plain_warmup=5):
     probs = [W.batch_instance(50_000 + i) for i in range(n_inst)]
     nodes = sum(p.nx * p.ny for p in probs)
     st = torch.cuda.Stream()
-    seg = [tuned_seg_rows(p, "f32", st) for p in probs]
+    seg = [tuned_seg_rows(p, "f32", st, fill_nodes=FILL_NODES) for p in probs]
     sims = [Lbrx(p, "f32", stream=st.cuda_stream, seg_rows=h) for p, h in zip(probs, seg)]
     b = Batch(sims)
     b.step(warmup)
@@ -155,7 +156,7 @@ def batched(n_inst, steps, warmup=30, plain_warmup=5):
         "ratio": round(mb / mp, 2),
         "batched_ms_per_step": round(wall_b / steps * 1e3, 3),
         "one_at_a_time_s": round(wall_p, 3),
-        "seg_rows_by_size_class": {f"{k[0]}": v for k, v in table().items() if k[1] == "f32"},
+        "seg_rows_by_size_class": {f"{k[0]}": v for k, v in table().items() if k[1] == "f32" and k[3] == "batch"},
     }
 
 

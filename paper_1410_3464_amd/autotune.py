@@ -2,10 +2,13 @@
 
 The kernel's work item is 64 columns by `seg_rows` rows, one wavefront.  Short
 items balance better on small lattices; long items repeat fewer ring rows (two
-per item) on large ones.  The best value depends on lattice size and storage
-precision, so it is measured: each candidate runs a few steps of a
-representative lattice on the GPU and the fastest is kept per (size class,
-precision, species count).  The choice changes speed only, never results.
+per item) on large ones.  The best value depends on lattice size, storage
+precision and on how full the device is, so it is measured: each candidate runs
+a few steps on the GPU and the fastest is kept per (size class, precision,
+species count, context).  Alone, a lattice is timed by itself; for batched runs
+(`fill_nodes` given) it is timed as a batch of copies holding about that many
+nodes, the situation of a simulation inside a large batch, where the device is
+full whatever the lattice size.  The choice changes speed only, never results.
 """
 from __future__ import annotations
 
@@ -20,29 +23,42 @@ def size_class(nx, ny):
     return 1 << max(6, int(round(math.log2(max(nx, ny)))))
 
 
-def tuned_seg_rows(prob, precision, stream=None, steps=20, warmup=3):
+MAX_COPIES = 32
+
+
+def tuned_seg_rows(prob, precision, stream=None, steps=20, warmup=3, fill_nodes=None):
     """seg_rows for `prob`'s size class, measured once per class on `stream`
-    (a torch.cuda.Stream); later calls return the cached choice."""
+    (a torch.cuda.Stream); later calls return the cached choice.  With
+    `fill_nodes`, the candidates are timed on a batch of copies of `prob`
+    (about fill_nodes nodes, at most MAX_COPIES copies) stepped by batched
+    launches."""
     import torch
 
-    from .lbrx import Lbrx
+    from .lbrx import Batch, Lbrx
 
-    key = (size_class(prob.nx, prob.ny), precision, prob.n_species)
+    copies = 1
+    if fill_nodes:
+        copies = max(1, min(MAX_COPIES, math.ceil(fill_nodes / (prob.nx * prob.ny))))
+    key = (size_class(prob.nx, prob.ny), precision, prob.n_species, "batch" if fill_nodes else "alone")
     if key in _cache:
         return _cache[key]
     st = stream if stream is not None else torch.cuda.Stream()
     best, best_ms = CANDIDATES[0], float("inf")
     for h in CANDIDATES:
-        sim = Lbrx(prob, precision, stream=st.cuda_stream, seg_rows=h)
-        sim.step(warmup)
+        sims = [Lbrx(prob, precision, stream=st.cuda_stream, seg_rows=h) for _ in range(copies)]
+        run = Batch(sims) if fill_nodes else sims[0]
+        run.step(warmup)
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record(st)
-        sim.step(steps)
+        run.step(steps)
         b.record(st)
         st.synchronize()
         ms = a.elapsed_time(b) / steps
-        sim.close()
+        if fill_nodes:
+            run.close()
+        for sim in sims:
+            sim.close()
         if ms < best_ms:
             best, best_ms = h, ms
     _cache[key] = best
@@ -50,5 +66,5 @@ def tuned_seg_rows(prob, precision, stream=None, steps=20, warmup=3):
 
 
 def table():
-    """The choices made so far: {(size class, precision, species): seg_rows}."""
+    """The choices made so far: {(size class, precision, species, context): seg_rows}."""
     return dict(_cache)

@@ -2187,6 +2187,8 @@ lbrx_status batch_build(lbrx_batch* b) {
       tab.push_back(((uint32_t)i << TAB_INST_SHIFT) | ((uint32_t)(x->steps % 6) << TAB_PHASE_SHIFT) | (uint32_t)k);
     b->base[i] = x->steps;
   }
+  // hipFree waits for the device to go idle, so launches still queued that
+  // read the old table (or replay the old graph) finish first
   if (b->dtable) (void)hipFree(b->dtable);
   b->dtable = nullptr;
   if (hipMalloc((void**)&b->dtable, tab.size() * 4) != hipSuccess)

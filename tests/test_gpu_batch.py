@@ -17,10 +17,13 @@ def _problems():
 
 @pytest.mark.parametrize("precision", ["f64", "f32", "f16dev"])
 def test_batch_equals_alone(precision):
-    """Four porous media of different sizes: 37 batched steps (one replay of
-    the captured 30-step graph, then single launches), one member stepped on
-    its own in between, 13 more batched steps: every field equal to running
-    each simulation alone for the same steps."""
+    """Four porous media of different sizes advanced by batched launches and,
+    independently, each alone by single launches; every field equal bit for
+    bit at every check.  The batch runs: 30 steps (the graph is captured and
+    replayed once), 30 more (second replay of the same graph), then one member
+    steps 5 times on its own (eager work between replays; the batch table and
+    graph are rebuilt), 67 batched steps (a new graph replayed twice, then
+    single launches), 30 more (third replay of the new graph)."""
     import torch
 
     from paper_1410_3464_amd.lbrx import Batch, Lbrx
@@ -28,23 +31,32 @@ def test_batch_equals_alone(precision):
     probs = _problems()
     st = torch.cuda.Stream()
     sims = [Lbrx(p, precision, stream=st.cuda_stream) for p in probs]
+    alone = [Lbrx(p, precision) for p in probs]
+    done = [0] * len(probs)
+
+    def check(tag):
+        for i, (p, g, a) in enumerate(zip(probs, sims, alone)):
+            a.step(g.steps_done - done[i])
+            done[i] = g.steps_done
+            G, A = g.fields(), a.fields()
+            for k in KEYS:
+                assert np.array_equal(G[k], A[k]), (tag, p.name, precision, k)
+            for k, v in A["ledger"].items():
+                assert np.array_equal(np.asarray(G["ledger"][k]), np.asarray(v)), (tag, p.name, k)
+
     b = Batch(sims)
-    b.step(37)
+    b.step(30)
+    check("first replay")
+    b.step(30)
+    check("second replay")
     sims[2].step(5)
-    b.step(13)
-    got = [s.fields() for s in sims]
+    check("member alone")
+    b.step(67)
+    check("rebuilt graph")
+    b.step(30)
+    check("third replay")
     b.close()
-    steps = [50, 50, 55, 50]
-    for p, g, n in zip(probs, got, steps):
-        a = Lbrx(p, precision)
-        a.step(n)
-        ref = a.fields()
-        for k in KEYS:
-            assert np.array_equal(g[k], ref[k]), (p.name, precision, k)
-        for k, v in ref["ledger"].items():
-            assert np.array_equal(np.asarray(g["ledger"][k]), np.asarray(v)), (p.name, k)
-        a.close()
-    for s in sims:
+    for s in sims + alone:
         s.close()
 
 
