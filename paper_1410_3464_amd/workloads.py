@@ -314,6 +314,33 @@ def batch_instance(seed, smin=64, smax=1024):
     return p
 
 
+def fracture(L=100, H=90, h0=30, g=1e-5, Da=0.001, Cs=1.0, molar_volume=300.0, k_sink=1e-3,
+             tau_g=1.0, J0=0.9):
+    """The dissolving fracture of App. A.3: an L x H box whose middle h0 rows
+    are an open channel between two walls of dissolvable mineral, periodic in
+    x, with one single-phase fluid (an ideal gas, no cohesion) driven by a body
+    acceleration g along x.  The dissolved species starts at zero; the walls
+    dissolve by the first-order law of Eq. A2 towards the saturation Cs with
+    rate constant k = Da D / h0 (D from Eq. 24 for tau_g, J0).  A first-order
+    sink of the dissolved species (rate k_sink) stands for the fresh solvent
+    that flows in through the paper's inlet, so that the walls stay far from
+    saturation and dissolve evenly along the channel; molar_volume sets how
+    many steps a wall row lasts.  Input description only."""
+    t = np.full((H, L), SOLID_D, np.uint8)
+    lo = (H - h0) // 2
+    t[lo:lo + h0] = FLUID
+    D = 0.5 * (1.0 - J0) * (tau_g - 0.5)
+    k = Da * D / h0
+    p = uniform_problem(L, H, periodic_x=True, periodic_y=False, rho1=1.0, rho2=0.0,
+                        species=[Species("M", tau_g=tau_g, J0=J0)], C0=np.zeros((1, H, L)),
+                        gbody=(g, 0.0),
+                        hom=[HomRxn("first_order", re=(0, -1), pr=(-1, -1), k=k_sink)],
+                        het=[HetRxn(reactant=0, product=-1, surface=(SOLID_D,), mode="mineral",
+                                    irreversible=False, k=k, C_eq=Cs, molar_volume=molar_volume)])
+    return p.copy(type0=t, V0=np.where(t > 0, 1.0, 0.0), rho1=np.where(t == FLUID, 1.0, 0.0),
+                  rho2=np.zeros((H, L)), name=f"fracture-{L}x{H}-h{h0}")
+
+
 def uniform_problem(nx, ny, periodic_x=True, periodic_y=True, rho1=1.0, rho2=0.0,
                     species=(), C0=None, ideal=True, **kw):
     """A uniform fluid box.  With ideal=True the liquid component is an ideal gas

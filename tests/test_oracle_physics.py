@@ -160,6 +160,41 @@ def test_wall_without_adhesion_is_neutral():
 
 
 # --------------------------------------------------------------------------
+# Dissolution: permeability of a dissolving fracture (App. A.3, Eq. A2, A3)
+# --------------------------------------------------------------------------
+def fracture_permeabilities(sim, steps, every, g, nu):
+    """Run `sim` for `steps`, reading the fields every `every` steps; for each
+    porosity eps (fluid fraction) keep the last reading: (eps -> (k_H, walls
+    flat)), with k_H = nu * (mean x-velocity over the whole box) / g."""
+    out = {}
+    for n in range(every, steps + 1, every):
+        sim.step(every)
+        F = sim.fields()
+        fl = F["type"] == W.FLUID
+        flat = bool((fl.all(1) | (~fl).all(1)).all())
+        out[round(float(fl.mean()), 9)] = (nu * float(F["ux"].mean()) / g, flat)
+    return out
+
+
+def test_fracture_dissolution_follows_cubic_law():
+    """A channel of 16 rows between two dissolvable walls in a 8 x 40 box,
+    driven by a body force, its walls dissolving by Eq. A2: the walls stay
+    flat, and each time they have receded the permeability k_H over the whole
+    box satisfies k_H / k_H0 = (eps / eps0)^3 (Eq. A3) within 0.5 %; the
+    first one equals (h^2/12)(h/H) within 1 % (halfway bounce-back)."""
+    g = 1e-5
+    p = W.fracture(L=8, H=40, h0=16, g=g, Da=0.02, molar_volume=10.0)
+    ks = fracture_permeabilities(OracleSim(p), 20000, 500, g, (1.0 - 0.5) / 3.0)
+    es = sorted(ks)
+    assert len(es) >= 5
+    assert all(flat for _, flat in ks.values())
+    e0, k0 = es[0], ks[es[0]][0]
+    assert abs(k0 / (16.0 ** 2 / 12 * 16 / 40) - 1) < 0.01
+    for e in es[:-1]:  # the last porosity may not have reached steady flow yet
+        assert abs(ks[e][0] / k0 / (e / e0) ** 3 - 1) < 0.005, (e, ks[e][0] / k0, (e / e0) ** 3)
+
+
+# --------------------------------------------------------------------------
 # Flow: Laplace law for a bubble (Appendix A.1, Eq. A1, Fig. A1)
 # --------------------------------------------------------------------------
 @pytest.mark.slow
