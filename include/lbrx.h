@@ -134,7 +134,7 @@ typedef struct {
   const double* rho2;       /* >= 0 at fluid nodes */
   const double* C0;         /* used at nodes that start liquid; may be NULL if n_species == 0 */
   /* work decomposition: rows per work item of the step kernel (each item is
-     64 columns by seg_rows rows, one wavefront), 1..30; 0 picks 16.  It
+     64 columns by seg_rows rows, one wavefront), 1..30; 0 picks 12.  It
      changes the speed, not the result. */
   int32_t seg_rows;
   /* effective mass psi_1 = sqrt(psi_prefactor (p_EOS - rho1/3) / G11) (Eq. 13).

@@ -1455,7 +1455,7 @@ __global__ __launch_bounds__(LSUM_THREADS) void k_ledger_sum(const double* led, 
 }
 
 // ---------------------------------------------------------------- host side
-constexpr int SEG_ROWS = 16;  // default rows per item (LBRX_SEG_ROWS overrides, 1..HMAX)
+constexpr int SEG_ROWS = 12;  // default rows per item (LBRX_SEG_ROWS overrides, 1..HMAX)
 
 template <typename T> using KFnT = void (*)(const LaunchArgs);
 
