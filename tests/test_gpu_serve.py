@@ -43,3 +43,29 @@ def test_admission_respects_memory_cap():
     spans = sorted((r.start, r.finish) for r in reqs)
     for (s0, f0), (s1, f1) in zip(spans, spans[1:]):
         assert s1 >= f0 - 1e-3
+
+
+def test_unstable_request_fails_alone():
+    """A request whose simulation diverges at its first step (the porous
+    instance with the literal Eq. 13 prefactor) is served in the same batch as
+    others of its precision and species count: it alone ends as failed, with
+    the instability named, and every other request completes with the fields
+    of its run alone."""
+    from paper_1410_3464_amd import serve
+    from paper_1410_3464_amd import workloads as W
+
+    reqs = serve.poisson_requests(5, 0.002, seed=5, steps=(40, 80), sizes=(64, 128), precisions=("f32",))
+    bad = W.batch_instance(7, smin=64, smax=96).copy(psi_prefactor=6.0)
+    reqs.insert(2, serve.Request(99, bad, 60, "f32", reqs[1].arrival))
+    mixed = serve.Server(tick=20, autotune=False, keep_fields=True).run(reqs)
+    alone_reqs = [r for r in serve.clone_requests(reqs) if r.rid != 99]
+    serve.run_plain(alone_reqs, keep_fields=True)
+    assert mixed["completed"] == len(reqs) - 1
+    failed = [r for r in reqs if r.status != "ok"]
+    assert [r.rid for r in failed] == [99] and "unstable" in failed[0].status
+    alone = {r.rid: r for r in alone_reqs}
+    for r in reqs:
+        if r.rid == 99:
+            continue
+        for k in KEYS:
+            assert np.array_equal(r.fields[k], alone[r.rid].fields[k]), (r.rid, k)
