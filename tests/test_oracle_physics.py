@@ -232,13 +232,13 @@ def test_laplace_law_bubble():
         area = ((rl_ - r1) / (rl_ - rv_)).sum()
         inv_r.append(1.0 / math.sqrt(area / math.pi))
         dps.append(P[n // 2, n // 2] - P[0, 0])
-        assert np.hypot(F["ux"], F["uy"]).max() < 0.05
+        assert np.hypot(F["ux"], F["uy"]).max() < GOLDEN["laplace"]["max_spurious_current"]
     A = np.vstack([inv_r, np.ones(4)]).T
     slope, icpt = np.linalg.lstsq(A, np.array(dps), rcond=None)[0]
     pred = A @ [slope, icpt]
     r2 = 1 - ((np.array(dps) - pred) ** 2).sum() / ((np.array(dps) - np.mean(dps)) ** 2).sum()
     assert r2 > 0.999
-    assert abs(slope / 0.667 - 1) < 0.05
+    assert abs(slope / GOLDEN["laplace"]["surface_tension"] - 1) < 0.05
 
 
 # --------------------------------------------------------------------------
