@@ -272,6 +272,7 @@ def main():
             "fluid_frac": round(counts["fluid"] / n, 4), "liquid_frac": round(counts["liquid"] / n, 4),
             "interface_frac": round(counts["interface"] / n, 4),
             "bytes_per_node": round(b_alg / n, 2),
+            "mflups": round(mlups * 0.5 * (counts["fluid"] + counts2["fluid"]) / n, 1),
         },
         "roofline": {
             "bound": "hbm",
@@ -282,6 +283,8 @@ def main():
             "traffic": None if traffic is None else round(traffic / 1e9, 4),
             "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE x 1, copy-calibrated)",
             "traffic_gbs": None if traffic is None else round(traffic / (kern_ms * 1e-3) / 1e9, 1),
+            "traffic_frac": None if traffic is None else round(traffic / (kern_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+            "waste": None if traffic is None else round(traffic / b_alg, 3),
             "kernel_ms": round(kern_ms, 4),
             "alg_bytes_per_launch": int(b_alg),
         },
