@@ -85,16 +85,16 @@ def measured_traffic(precision, n):
 def serving(n, interarrival):
     """Poisson arrivals of many-simulation requests (square porous lattices of
     side 64-1024, 200-2000 steps, FP32 or FP16-deviation storage), served by
-    the batched loop and, for comparison, one at a time with plain runs."""
+    the batched loop and, for comparison, one at a time with plain FP32 runs."""
     from paper_1410_3464_amd import serve
 
     reqs = serve.poisson_requests(n, interarrival, seed=11)
     batched = serve.Server(tick=60).run(reqs)
-    plain = serve.run_plain(serve.clone_requests(reqs))
+    plain = serve.run_plain(serve.clone_requests(reqs), precision="f32")
     print(f"# serving batched {batched} plain {plain}", file=sys.stderr, flush=True)
     return {
         "workload": f"{n} requests, Poisson arrivals every {interarrival * 1e3:.0f} ms on average, "
-                    "porous lattices 64^2-1024^2, 200-2000 steps, f32 or f16dev",
+                    "porous lattices 64^2-1024^2, 200-2000 steps, f32 or f16dev; plain: one at a time in f32",
         "batched": batched, "plain": plain,
         "p50_speedup": round(plain["p50_ms"] / batched["p50_ms"], 2),
         "p99_speedup": round(plain["p99_ms"] / batched["p99_ms"], 2),

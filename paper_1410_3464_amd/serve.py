@@ -10,9 +10,9 @@ their work overlaps on the device.  A request completes when its steps are
 done; its fields are read back and its memory freed.
 
 `run_plain` serves the same requests one at a time in arrival order, each
-stepped alone: the reference the batched server is compared with (latency
-from arrival to completion, p50 / p99, and aggregate lattice updates per
-second).
+stepped alone (optionally all with the plain FP32 kernels): the reference the
+batched server is compared with (latency from arrival to completion, p50 /
+p99, and aggregate lattice updates per second).
 """
 from __future__ import annotations
 
@@ -155,8 +155,9 @@ class Server:
         return summarize(requests, makespan)
 
 
-def run_plain(requests, keep_fields=False):
-    """The same requests one at a time in arrival order, each stepped alone."""
+def run_plain(requests, keep_fields=False, precision=None):
+    """The same requests one at a time in arrival order, each stepped alone
+    (in `precision` if given, e.g. the plain FP32 kernels, else in its own)."""
     import torch
 
     from .lbrx import Lbrx, LbrxError
@@ -168,7 +169,7 @@ def run_plain(requests, keep_fields=False):
         if wait > 0:
             time.sleep(wait)
         r.start = time.perf_counter() - t0
-        sim = Lbrx(r.prob, r.precision, stream=stream.cuda_stream)
+        sim = Lbrx(r.prob, precision or r.precision, stream=stream.cuda_stream)
         sim.step(r.steps)
         try:
             sim.sync()
