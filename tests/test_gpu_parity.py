@@ -75,11 +75,9 @@ def test_fp64_parity_small(which):
         _run_pair(porous, "f64", [1, 50, 300, 600], 1e-12)
 
 
-def test_fp64_parity_events():
+def events_problem():
     """A dissolvable grain in liquid next to a precipitate wall, with fast surface
-    kinetics: the grain dissolves, precipitate grows from the wall and displaces
-    fluid, interfaces move (every amendment path of the step runs); FP64 parity
-    holds throughout."""
+    kinetics (every amendment path of the step runs within 300 steps)."""
     n = 40
     a, b, R = W.EOS_PAPER
     T = 0.75 * W.critical_temperature(a, b, R)
@@ -106,6 +104,15 @@ def test_fp64_parity_events():
         het=[W.HetRxn(1, 2, (W.SOLID_D,), "consumes", True, 1.0, 0.0, 1.0),
              W.HetRxn(3, -1, (W.SOLID_D, W.SOLID_F), "grows", True, 0.3, 0.0, 2.0)],
         type0=t0, V0=np.where(grain, 0.3, np.where(t0 == W.SOLID_F, 1.0, 0.0)), rho1=rho1, rho2=rho2, C0=C0)
+    return prob
+
+
+def test_fp64_parity_events():
+    """A dissolvable grain in liquid next to a precipitate wall, with fast surface
+    kinetics: the grain dissolves, precipitate grows from the wall and displaces
+    fluid, interfaces move (every amendment path of the step runs); FP64 parity
+    holds throughout."""
+    prob = events_problem()
     rep = _run_pair(prob, "f64", [5, 50, 150, 300], 1e-12)
     o = OracleSim(prob)
     o.step(300)
@@ -157,6 +164,44 @@ def test_parity_species_counts(ns, precision):
         _run_pair(prob, "f64", [1, 50, 300], 1e-12)
     else:
         _run_pair(prob, "f32", [1, 10], 1e-5)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32", "f16dev"])
+def test_runs_are_deterministic(precision):
+    """The event-heavy case run twice for 300 steps: fields, node types and
+    liquid marks bit-identical, event counts equal.  Fields depend on no
+    floating-point atomic; the balance sums of rare events are added with LDS
+    atomics in an order the hardware picks, so they are compared to 1e-12."""
+    Lbrx = _gpu()
+    prob = events_problem()
+    out = []
+    for _ in range(2):
+        g = Lbrx(prob, precision)
+        g.step(300)
+        out.append(g.fields())
+        g.close()
+    a, b = out
+    for k in ("rho1", "rho2", "ux", "uy", "C", "V", "type", "liquid"):
+        assert np.array_equal(a[k], b[k]), k
+    for k, v in a["ledger"].items():
+        np.testing.assert_allclose(np.asarray(b["ledger"][k]), np.asarray(v), rtol=1e-12, atol=1e-300, err_msg=k)
+
+
+def test_full_lattice_runs_are_deterministic():
+    """The 4096 x 4096 porous medium in FP32, twice 20 steps: every field
+    bit-identical (the launch schedule over 256 CUs differs between runs)."""
+    Lbrx = _gpu()
+    prob = W.config2()
+    out = []
+    for _ in range(2):
+        g = Lbrx(prob, "f32")
+        g.step(20)
+        F = g.fields()
+        out.append({k: F[k] for k in ("rho1", "rho2", "ux", "uy", "C", "V", "type", "liquid")})
+        g.close()
+        del F
+    for k in out[0]:
+        assert np.array_equal(out[0][k], out[1][k]), k
 
 
 def test_fp32_parity_droplet():
