@@ -200,6 +200,26 @@ lbrx_status lbrx_sync(lbrx_ctx* ctx);
 /* Waits, then fills the caller's host buffers (FP64 whatever the precision). */
 lbrx_status lbrx_fields(lbrx_ctx* ctx, lbrx_fields_out* out);
 
+/* Checkpoint and resume of the whole simulation state, so that a run of the
+ * Sec. 4.7 procedure can stop and continue: the populations, node status
+ * words (types, liquid marks, neighbour masks, 16-bit reference codes), solid
+ * volumes, balance records, the lagged rho_max of Sec. 4.5 and the step
+ * count.  The parameters are not part of the state.
+ *   lbrx_state_bytes: size of the state of `ctx` in bytes (into *bytes).
+ *   lbrx_save_state:  synchronises, then copies the state into the caller's
+ *     host buffer `buf` of `bytes` (>= lbrx_state_bytes); LBRX_E_INVAL if too
+ *     small; a failed context cannot be saved (its sticky error is returned).
+ *   lbrx_load_state:  replaces the state of `ctx` by a saved one.  `ctx` must
+ *     have been created with the same lattice size, precision, species count
+ *     and seg_rows (LBRX_E_INVAL otherwise, state unchanged); other
+ *     parameters may differ and apply from the next step.  Enqueued on the
+ *     context's stream after its pending work; returns after the copy.
+ * Loading a state saved after N steps and stepping M more gives fields bit
+ * for bit equal to N + M steps without the checkpoint. */
+lbrx_status lbrx_state_bytes(const lbrx_ctx* ctx, uint64_t* bytes);
+lbrx_status lbrx_save_state(lbrx_ctx* ctx, void* buf, uint64_t bytes);
+lbrx_status lbrx_load_state(lbrx_ctx* ctx, const void* buf, uint64_t bytes);
+
 /* Steps taken so far. */
 int64_t lbrx_step_count(const lbrx_ctx* ctx);
 

@@ -2079,6 +2079,130 @@ lbrx_status lbrx_sync(lbrx_ctx* x) {
   return LBRX_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// ------------------------------------------------------------ checkpoints
+// State blob: a header naming the layout, then the current populations, status
+// words, solute code words, solid volumes, rho_max partials and balance records.
+struct StateHeader {
+  char magic[8];
+  uint32_t abi;
+  int32_t nx, ny, pitch, precision, ns, seg_rows, nitems;
+  int64_t steps;
+  uint64_t fbytes, gbytes, tbytes, cbytes, vbytes, rbytes, lbytes;
+};
+static const char STATE_MAGIC[8] = {'L', 'B', 'R', 'X', 'S', 'T', '0', '1'};
+
+StateHeader state_header(const lbrx_ctx* x) {
+  const KConst& c = x->c;
+  StateHeader h{};
+  std::memcpy(h.magic, STATE_MAGIC, 8);
+  h.abi = LBRX_ABI_VERSION;
+  h.nx = c.nx;
+  h.ny = c.ny;
+  h.pitch = c.pitch;
+  h.precision = x->precision;
+  h.ns = c.ns;
+  h.seg_rows = c.seg_rows;
+  h.nitems = c.nitems;
+  h.steps = x->steps;
+  h.fbytes = c.fbytes;
+  h.gbytes = c.gbytes;
+  h.tbytes = c.tbytes;
+  h.cbytes = x->cw[0] ? c.cbytes : 0;
+  h.vbytes = (uint64_t)c.plane * 8;
+  h.rbytes = (uint64_t)RM_WORDS * 8;
+  h.lbytes = (uint64_t)c.nitems * NLED * 8;
+  return h;
+}
+uint64_t state_size(const StateHeader& h) {
+  return sizeof(StateHeader) + h.fbytes + h.gbytes + h.tbytes + h.cbytes + h.vbytes + h.rbytes + h.lbytes;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbrx_status lbrx_state_bytes(const lbrx_ctx* x, uint64_t* bytes) {
+  if (!x || !bytes) return LBRX_E_INVAL;
+  *bytes = state_size(state_header(x));
+  return LBRX_OK;
+}
+
+lbrx_status lbrx_save_state(lbrx_ctx* x, void* buf, uint64_t bytes) {
+  if (!x || !buf) return LBRX_E_INVAL;
+  const StateHeader h = state_header(x);
+  if (bytes < state_size(h)) return set_err(x, LBRX_E_INVAL, "state buffer too small");
+  const lbrx_status st = lbrx_sync(x);
+  if (st != LBRX_OK) return st;
+  char* p = (char*)buf;
+  std::memcpy(p, &h, sizeof h);
+  p += sizeof h;
+  const int cur = x->cur;
+  auto get = [&](const void* src, uint64_t n) -> hipError_t {
+    if (n == 0) return hipSuccess;
+    const hipError_t e = hipMemcpy(p, src, n, hipMemcpyDeviceToHost);
+    p += n;
+    return e;
+  };
+  HIPCHK(x, get(x->f[cur], h.fbytes));
+  HIPCHK(x, get(x->g[cur], h.gbytes));
+  HIPCHK(x, get(x->t[cur], h.tbytes));
+  HIPCHK(x, get(x->cw[cur], h.cbytes));
+  HIPCHK(x, get(x->V, h.vbytes));
+  HIPCHK(x, get(x->rmax, h.rbytes));
+  HIPCHK(x, get(x->led, h.lbytes));
+  return LBRX_OK;
+}
+
+lbrx_status lbrx_load_state(lbrx_ctx* x, const void* buf, uint64_t bytes) {
+  if (!x || !buf) return LBRX_E_INVAL;
+  if (x->failed) return set_err(x, LBRX_E_STATE, "context failed earlier: " + x->msg);
+  StateHeader h;
+  if (bytes < sizeof h) return set_err(x, LBRX_E_INVAL, "state buffer too small");
+  std::memcpy(&h, buf, sizeof h);
+  StateHeader mine = state_header(x);
+  mine.steps = h.steps;
+  if (std::memcmp(&h, &mine, sizeof h) != 0)
+    return set_err(x, LBRX_E_INVAL, "the state was saved from a context of another layout "
+                                    "(lattice size, precision, species count, seg_rows or ABI version)");
+  if (h.steps < 0 || bytes < state_size(h)) return set_err(x, LBRX_E_INVAL, "state buffer too small");
+  HIPCHK(x, hipSetDevice(x->device));
+  HIPCHK(x, hipStreamSynchronize(x->stream));
+  const char* p = (const char*)buf + sizeof h;
+  const int cur = (int)(h.steps & 1);
+  // the populations go into both buffers, as at create: slots that the next
+  // steps do not write hold defined values
+  auto put2 = [&](void* const (&dst)[2], uint64_t n) -> hipError_t {
+    if (n == 0) return hipSuccess;
+    hipError_t e = hipMemcpy(dst[cur], p, n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dst[1 - cur], p, n, hipMemcpyHostToDevice);
+    p += n;
+    return e;
+  };
+  auto put = [&](void* dst, uint64_t n) -> hipError_t {
+    const hipError_t e = hipMemcpy(dst, p, n, hipMemcpyHostToDevice);
+    p += n;
+    return e;
+  };
+  void* const fb[2] = {x->f[0], x->f[1]};
+  void* const gb[2] = {x->g[0], x->g[1]};
+  void* const tb[2] = {x->t[0], x->t[1]};
+  void* const cb[2] = {x->cw[0], x->cw[1]};
+  HIPCHK(x, put2(fb, h.fbytes));
+  HIPCHK(x, put2(gb, h.gbytes));
+  HIPCHK(x, put2(tb, h.tbytes));
+  HIPCHK(x, put2(cb, h.cbytes));
+  HIPCHK(x, put(x->V, h.vbytes));
+  HIPCHK(x, put(x->rmax, h.rbytes));
+  HIPCHK(x, put(x->led, h.lbytes));
+  x->steps = h.steps;
+  x->cur = cur;
+  return LBRX_OK;
+}
+
 lbrx_status lbrx_fields(lbrx_ctx* x, lbrx_fields_out* o) {
   if (!x || !o) return LBRX_E_INVAL;
   const lbrx_status st = lbrx_sync(x);

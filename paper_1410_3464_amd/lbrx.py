@@ -28,7 +28,7 @@ STATUS = {0: "LBRX_OK", 1: "LBRX_E_INVAL", 2: "LBRX_E_NOMEM", 3: "LBRX_E_DEVICE"
 SYMBOLS = ("lbrx_create", "lbrx_create_error", "lbrx_step", "lbrx_sync", "lbrx_fields",
            "lbrx_step_count", "lbrx_stream", "lbrx_destroy", "lbrx_last_error",
            "lbrx_status_string", "lbrx_batch_create", "lbrx_batch_step", "lbrx_batch_last_error",
-           "lbrx_batch_destroy")
+           "lbrx_batch_destroy", "lbrx_state_bytes", "lbrx_save_state", "lbrx_load_state")
 
 
 class HomRxn(C.Structure):
@@ -110,6 +110,12 @@ def load_library(path=LIB_PATH):
     lib.lbrx_last_error.argtypes = [C.c_void_p]
     lib.lbrx_status_string.restype = C.c_char_p
     lib.lbrx_status_string.argtypes = [C.c_int]
+    lib.lbrx_state_bytes.restype = C.c_int
+    lib.lbrx_state_bytes.argtypes = [C.c_void_p, C.POINTER(C.c_uint64)]
+    lib.lbrx_save_state.restype = C.c_int
+    lib.lbrx_save_state.argtypes = [C.c_void_p, C.c_void_p, C.c_uint64]
+    lib.lbrx_load_state.restype = C.c_int
+    lib.lbrx_load_state.argtypes = [C.c_void_p, C.c_void_p, C.c_uint64]
     lib.lbrx_batch_create.restype = C.c_int
     lib.lbrx_batch_create.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_void_p)]
     lib.lbrx_batch_step.restype = C.c_int
@@ -229,6 +235,19 @@ class Lbrx:
                    liquid=lq.reshape(ny, nx), V=V.reshape(ny, nx), rho_max_prev=float(rmax[0]))
         out["ledger"] = unpack_ledger(led)
         return out
+
+    def save_state(self):
+        """The whole simulation state (lbrx_save_state) as a uint8 array."""
+        n = C.c_uint64()
+        self._check(self._lib.lbrx_state_bytes(self._h, C.byref(n)))
+        buf = np.empty(n.value, np.uint8)
+        self._check(self._lib.lbrx_save_state(self._h, buf.ctypes.data, n.value))
+        return buf
+
+    def load_state(self, buf):
+        """Replace the state by one returned by save_state (lbrx_load_state)."""
+        buf = np.ascontiguousarray(buf, np.uint8)
+        self._check(self._lib.lbrx_load_state(self._h, buf.ctypes.data, buf.size))
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
