@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define LBRX_ABI_VERSION 3u
+#define LBRX_ABI_VERSION 4u
 #define LBRX_MAX_SPECIES 8
 #define LBRX_MAX_RXN 8
 
@@ -141,6 +141,16 @@ typedef struct {
      0 selects 2, the value for which the weights of Eq. 11 reproduce the EOS
      of Eq. 12; 6 is the prefactor printed in Eq. 13.  Otherwise > 0. */
   double psi_prefactor;
+  /* device memory: every device buffer of the context (and of a batch built
+     on it) comes from dev_alloc(bytes, alloc_user) and goes back through
+     dev_free(ptr, alloc_user), e.g. a framework's caching allocator; both
+     NULL: hipMalloc / hipFree.  The memory must be device memory of the
+     current device, 256-byte aligned; dev_alloc returns NULL on failure
+     (LBRX_E_NOMEM).  Buffers are returned only after the context's stream
+     has drained.  Set both or neither. */
+  void* (*dev_alloc)(uint64_t bytes, void* user);
+  void (*dev_free)(void* ptr, void* user);
+  void* alloc_user;
 } lbrx_params;
 
 /* Cumulative balances, FP64.  With M_s the total of component s and S_k the

@@ -1511,9 +1511,29 @@ struct lbrx_ctx {
   KT<float> kf{};
   KFnT<double> step64 = nullptr, export64 = nullptr;
   KFnT<float> step32 = nullptr, export32 = nullptr;
+  void* (*dev_alloc)(uint64_t, void*) = nullptr;  // caller's device allocator (else hipMalloc)
+  void (*dev_free)(void*, void*) = nullptr;
+  void* alloc_user = nullptr;
 };
 
 namespace {
+
+// Device memory of a context: the caller's allocator when one was given, else
+// hipMalloc / hipFree.  A zero-byte request yields a null pointer.
+bool ctx_alloc(lbrx_ctx* x, void** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) return true;
+  if (x->dev_alloc) {
+    *p = x->dev_alloc((uint64_t)n, x->alloc_user);
+    return *p != nullptr;
+  }
+  return hipMalloc(p, n) == hipSuccess;
+}
+void ctx_free(lbrx_ctx* x, void* p) {
+  if (!p) return;
+  if (x->dev_free) x->dev_free(p, x->alloc_user);
+  else (void)hipFree(p);
+}
 
 lbrx_status set_err(lbrx_ctx* c, lbrx_status s, const std::string& m) {
   if (c) {
@@ -1566,6 +1586,7 @@ std::string validate(const lbrx_params* p) {
       return "surface_factor must be positive and finite";
   }
   if (!(p->psi_prefactor >= 0.0 && p->psi_prefactor < 1e300)) return "psi_prefactor must be 0 (default) or positive";
+  if (!p->dev_alloc != !p->dev_free) return "dev_alloc and dev_free must be given together";
   for (int r = 0; r < p->n_het; ++r) {
     const lbrx_het_rxn& h = p->het[r];
     if (h.reactant < 0 || h.reactant >= ns || h.product < -1 || h.product >= ns) return "species index out of range";
@@ -1874,6 +1895,9 @@ lbrx_status lbrx_create(const lbrx_params* p, void* hip_stream, lbrx_ctx** out) 
     return LBRX_E_INVAL;
   }
   lbrx_ctx* x = new lbrx_ctx();
+  x->dev_alloc = p->dev_alloc;
+  x->dev_free = p->dev_free;
+  x->alloc_user = p->alloc_user;
   KConst& c = x->c;
   c.nx = p->nx;
   c.ny = p->ny;
@@ -1983,13 +2007,13 @@ lbrx_status lbrx_create(const lbrx_params* p, void* hip_stream, lbrx_ctx** out) 
   const size_t plane = (size_t)c.plane;
   const size_t fbytes = f_elems(c) * x->esz, gbytes = g_elems(c) * x->esz;
   for (int i = 0; i < 2; ++i) {
-    if (hipMalloc(&x->f[i], fbytes) != hipSuccess || hipMalloc(&x->g[i], gbytes) != hipSuccess ||
-        hipMalloc((void**)&x->t[i], plane * 4) != hipSuccess || hipMalloc((void**)&x->cw[i], c.cbytes) != hipSuccess)
+    if (!ctx_alloc(x, &x->f[i], fbytes) || !ctx_alloc(x, &x->g[i], gbytes) ||
+        !ctx_alloc(x, (void**)&x->t[i], plane * 4) || !ctx_alloc(x, (void**)&x->cw[i], c.cbytes))
       return fail(LBRX_E_NOMEM, "device allocation of the populations failed");
   }
-  if (hipMalloc((void**)&x->V, plane * 8) != hipSuccess || hipMalloc((void**)&x->rmax, RM_WORDS * 8) != hipSuccess ||
-      hipMalloc((void**)&x->led, (size_t)c.nitems * NLED * 8) != hipSuccess ||
-      hipMalloc((void**)&x->ledsum, NLED * 8) != hipSuccess || hipMalloc((void**)&x->err, 2 * 4) != hipSuccess)
+  if (!ctx_alloc(x, (void**)&x->V, plane * 8) || !ctx_alloc(x, (void**)&x->rmax, RM_WORDS * 8) ||
+      !ctx_alloc(x, (void**)&x->led, (size_t)c.nitems * NLED * 8) || !ctx_alloc(x, (void**)&x->ledsum, NLED * 8) ||
+      !ctx_alloc(x, (void**)&x->err, 2 * 4))
     return fail(LBRX_E_NOMEM, "device allocation of the state failed");
 
   // initial state (host staging, then one copy each)
@@ -2042,7 +2066,8 @@ lbrx_status lbrx_create(const lbrx_params* p, void* hip_stream, lbrx_ctx** out) 
   unsigned int er[2] = {0u, 0xffffffffu};
   if (e == hipSuccess) e = hipMemcpy(x->err, er, sizeof er, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(x->led, 0, (size_t)c.nitems * NLED * 8);
-  if (e == hipSuccess) e = hipMalloc(&x->dargs, args_bytes(x->precision));
+  if (e == hipSuccess && !ctx_alloc(x, &x->dargs, args_bytes(x->precision)))
+    return fail(LBRX_E_NOMEM, "device allocation of the kernel arguments failed");
   if (e == hipSuccess) e = upload_args(x);
   if (e != hipSuccess) return fail(LBRX_E_DEVICE, std::string("initial copy failed: ") + hipGetErrorString(e));
   *out = x;
@@ -2210,7 +2235,8 @@ lbrx_status lbrx_fields(lbrx_ctx* x, lbrx_fields_out* o) {
   const KConst& c = x->c;
   const size_t plane = (size_t)c.plane;
   if (!x->out) {
-    HIPCHK(x, hipMalloc((void**)&x->out, (4 + (size_t)c.ns) * plane * 8));
+    if (!ctx_alloc(x, (void**)&x->out, (4 + (size_t)c.ns) * plane * 8))
+      return set_err(x, LBRX_E_NOMEM, "device allocation of the read-out planes failed");
     HIPCHK(x, upload_args(x));
   }
   HIPCHK(x, hipMemsetAsync(x->out, 0, (4 + (size_t)c.ns) * plane * 8, x->stream));
@@ -2311,11 +2337,14 @@ lbrx_status batch_build(lbrx_batch* b) {
       tab.push_back(((uint32_t)i << TAB_INST_SHIFT) | ((uint32_t)(x->steps % 6) << TAB_PHASE_SHIFT) | (uint32_t)k);
     b->base[i] = x->steps;
   }
-  // hipFree waits for the device to go idle, so launches still queued that
-  // read the old table (or replay the old graph) finish first
-  if (b->dtable) (void)hipFree(b->dtable);
+  // launches still queued that read the old table (or replay the old graph)
+  // finish before it is returned
+  if (b->dtable) {
+    (void)hipStreamSynchronize(b->stream);
+    ctx_free(b->ctx[0], b->dtable);
+  }
   b->dtable = nullptr;
-  if (hipMalloc((void**)&b->dtable, tab.size() * 4) != hipSuccess)
+  if (!ctx_alloc(b->ctx[0], (void**)&b->dtable, tab.size() * 4))
     return batch_err(b, LBRX_E_NOMEM, "device allocation of the batch table failed");
   if (hipMemcpy(b->dtable, tab.data(), tab.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
     return batch_err(b, LBRX_E_DEVICE, "copy of the batch table failed");
@@ -2369,7 +2398,7 @@ lbrx_status lbrx_batch_create(lbrx_ctx* const* ctxs, int n, lbrx_batch** out) {
   }
   std::vector<void*> inst(n);
   for (int i = 0; i < n; ++i) inst[i] = ctxs[i]->dargs;
-  if (hipMalloc((void**)&b->dinst, n * sizeof(void*)) != hipSuccess) {
+  if (!ctx_alloc(b->ctx[0], (void**)&b->dinst, n * sizeof(void*))) {
     delete b;
     return LBRX_E_NOMEM;
   }
@@ -2434,8 +2463,8 @@ lbrx_status lbrx_batch_destroy(lbrx_batch* b) {
   (void)hipSetDevice(b->device);
   if (b->stream) (void)hipStreamSynchronize(b->stream);
   batch_drop_graph(b);
-  if (b->dtable) (void)hipFree(b->dtable);
-  if (b->dinst) (void)hipFree(b->dinst);
+  ctx_free(b->ctx[0], b->dtable);
+  ctx_free(b->ctx[0], b->dinst);
   delete b;
   return LBRX_OK;
 }
@@ -2449,18 +2478,18 @@ lbrx_status lbrx_destroy(lbrx_ctx* x) {
   (void)hipSetDevice(x->device);
   if (x->stream) (void)hipStreamSynchronize(x->stream);
   for (int i = 0; i < 2; ++i) {
-    if (x->f[i]) (void)hipFree(x->f[i]);
-    if (x->g[i]) (void)hipFree(x->g[i]);
-    if (x->t[i]) (void)hipFree(x->t[i]);
-    if (x->cw[i]) (void)hipFree(x->cw[i]);
+    ctx_free(x, x->f[i]);
+    ctx_free(x, x->g[i]);
+    ctx_free(x, x->t[i]);
+    ctx_free(x, x->cw[i]);
   }
-  if (x->V) (void)hipFree(x->V);
-  if (x->rmax) (void)hipFree(x->rmax);
-  if (x->led) (void)hipFree(x->led);
-  if (x->ledsum) (void)hipFree(x->ledsum);
-  if (x->err) (void)hipFree(x->err);
-  if (x->out) (void)hipFree(x->out);
-  if (x->dargs) (void)hipFree(x->dargs);
+  ctx_free(x, x->V);
+  ctx_free(x, x->rmax);
+  ctx_free(x, x->led);
+  ctx_free(x, x->ledsum);
+  ctx_free(x, x->err);
+  ctx_free(x, x->out);
+  ctx_free(x, x->dargs);
   if (x->own_stream && x->stream) (void)hipStreamDestroy(x->stream);
   delete x;
   return LBRX_OK;

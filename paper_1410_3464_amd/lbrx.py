@@ -14,7 +14,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbrx.so")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 MAXS = 8
 MAXR = 8
 F64, F32, F16DEV, BF16DEV = 0, 1, 2, 3
@@ -57,7 +57,31 @@ class Params(C.Structure):
         ("n_het", C.c_int32), ("het", HetRxn * MAXR),
         ("node_type", C.c_void_p), ("V0", C.c_void_p), ("rho1", C.c_void_p), ("rho2", C.c_void_p),
         ("C0", C.c_void_p), ("seg_rows", C.c_int32), ("psi_prefactor", C.c_double),
+        ("dev_alloc", C.c_void_p), ("dev_free", C.c_void_p), ("alloc_user", C.c_void_p),
     ]
+
+
+# device allocator callbacks of lbrx_params
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_uint64, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+def torch_allocator(stream=None):
+    """(dev_alloc, dev_free) callbacks drawing the context's device memory from
+    PyTorch's caching allocator (associated with `stream`, a HIP stream handle,
+    if given).  Keep the returned pair alive as long as the context."""
+    import torch
+
+    def alloc(n, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(n), stream=stream)
+        except RuntimeError:  # out of memory: the library reports LBRX_E_NOMEM
+            return None
+
+    def free(ptr, user):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return ALLOC_FN(alloc), FREE_FN(free)
 
 
 LEDGER_FIELDS = [("mass_src", 2), ("mass_inj", 2), ("mass_rem", 2), ("sol_src", MAXS),
@@ -187,13 +211,22 @@ def _ptr(a):
 class Lbrx:
     """One GPU simulation of a workloads.Problem (a context of the C ABI)."""
 
-    def __init__(self, prob, precision="f64", stream=None, seg_rows=0):
+    def __init__(self, prob, precision="f64", stream=None, seg_rows=0, allocator=None):
+        """allocator: None (the library's hipMalloc) or "torch" (PyTorch's
+        caching allocator supplies the device memory)."""
         lib = load_library()
         self._lib = lib
         self.prob = prob
         self.nx, self.ny, self.ns = prob.nx, prob.ny, prob.n_species
         self.precision = precision
         params, keep = make_params(prob, precision, seg_rows)
+        self._hooks = None
+        if allocator == "torch":
+            self._hooks = torch_allocator(stream)
+            params.dev_alloc = C.cast(self._hooks[0], C.c_void_p)
+            params.dev_free = C.cast(self._hooks[1], C.c_void_p)
+        elif allocator is not None:
+            raise ValueError(f"unknown allocator {allocator!r}")
         h = C.c_void_p()
         st = lib.lbrx_create(C.byref(params), stream, C.byref(h))
         if st != 0:

@@ -44,10 +44,10 @@ def test_binding_struct_layout_matches_header():
 #include <stddef.h>
 #include "lbrx.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(lbrx_params), offsetof(lbrx_params, hom),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(lbrx_params), offsetof(lbrx_params, hom),
          offsetof(lbrx_params, het), offsetof(lbrx_params, node_type), sizeof(lbrx_ledger),
          sizeof(lbrx_fields_out), sizeof(lbrx_het_rxn), sizeof(lbrx_hom_rxn),
-         offsetof(lbrx_params, psi_prefactor));
+         offsetof(lbrx_params, psi_prefactor), offsetof(lbrx_params, alloc_user));
   return 0;
 }
 '''
@@ -59,7 +59,8 @@ int main(void) {
         got = [int(v) for v in subprocess.check_output([exe]).split()]
     want = [ctypes.sizeof(lbrx.Params), lbrx.Params.hom.offset, lbrx.Params.het.offset,
             lbrx.Params.node_type.offset, lbrx.LEDGER_LEN * 8, ctypes.sizeof(lbrx.FieldsOut),
-            ctypes.sizeof(lbrx.HetRxn), ctypes.sizeof(lbrx.HomRxn), lbrx.Params.psi_prefactor.offset]
+            ctypes.sizeof(lbrx.HetRxn), ctypes.sizeof(lbrx.HomRxn), lbrx.Params.psi_prefactor.offset,
+            lbrx.Params.alloc_user.offset]
     assert got == want
 
 
