@@ -209,10 +209,12 @@ def config0(seed=0):
 
 def porous_medium(nx, ny, seed, porosity=0.55, rmin=8.0, rmax=24.0, reactive_frac=0.2,
                   gas_frac=0.3, bmin=6.0, bmax=16.0):
-    """Random overlapping disks (periodic in x) until the porosity target; grains
-    chosen in random order become dissolvable (D) until the reactive fraction of solid
-    nodes is reached, the rest inert; vapour bubbles on pore nodes until gas_frac of
-    the pore space.  Returns (type0, gas) as arrays."""
+    """Random overlapping disks (periodic in x) until the porosity target (the
+    last disk keeps only as many of its new nodes, nearest its centre, as the
+    target needs, so that small lattices keep the target too); grains chosen
+    in random order become dissolvable (D) until the reactive fraction of solid
+    nodes is reached, the rest inert; vapour bubbles on pore nodes until
+    gas_frac of the pore space.  Returns (type0, gas, rng)."""
     rng = _rng(seed)
     grain_id = np.full((ny, nx), -1, np.int64)
     n_solid = 0
@@ -224,8 +226,15 @@ def porous_medium(nx, ny, seed, porosity=0.55, rmin=8.0, rmax=24.0, reactive_fra
         r = rng.uniform(rmin, rmax)
         _, ys, xs = _stamp_disk(grain_id, cx, cy, r, True, False)
         new = grain_id[ys, xs] < 0
-        grain_id[ys[new], xs[new]] = gid
-        n_solid += int(new.sum())
+        ys, xs = ys[new], xs[new]
+        need = int(math.ceil(target - n_solid))
+        if len(ys) > need:
+            dx = np.abs(xs - cx)
+            dx = np.minimum(dx, nx - dx)
+            keep = np.argsort(dx * dx + (ys - cy) ** 2, kind="stable")[:need]
+            ys, xs = ys[keep], xs[keep]
+        grain_id[ys, xs] = gid
+        n_solid += len(ys)
         gid += 1
     type0 = np.where(grain_id >= 0, SOLID_INERT, FLUID).astype(np.uint8)
     counts = np.bincount(grain_id[grain_id >= 0].ravel(), minlength=gid)
