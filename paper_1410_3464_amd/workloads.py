@@ -209,12 +209,13 @@ def config0(seed=0):
 
 def porous_medium(nx, ny, seed, porosity=0.55, rmin=8.0, rmax=24.0, reactive_frac=0.2,
                   gas_frac=0.3, bmin=6.0, bmax=16.0):
-    """Random overlapping disks (periodic in x) until the porosity target (the
-    last disk keeps only as many of its new nodes, nearest its centre, as the
-    target needs, so that small lattices keep the target too); grains chosen
-    in random order become dissolvable (D) until the reactive fraction of solid
-    nodes is reached, the rest inert; vapour bubbles on pore nodes until
-    gas_frac of the pore space.  Returns (type0, gas, rng)."""
+    """Random overlapping disks (periodic in x) until the porosity target; a
+    disk that would overshoot the target by more than 0.5 % of the lattice (on
+    small lattices a single grain can) is shrunk to the largest radius that
+    does not, and ends the loop; grains chosen in random order become
+    dissolvable (D) until the reactive fraction of solid nodes is reached, the
+    rest inert; vapour bubbles on pore nodes until gas_frac of the pore space.
+    Returns (type0, gas, rng)."""
     rng = _rng(seed)
     grain_id = np.full((ny, nx), -1, np.int64)
     n_solid = 0
@@ -226,16 +227,24 @@ def porous_medium(nx, ny, seed, porosity=0.55, rmin=8.0, rmax=24.0, reactive_fra
         r = rng.uniform(rmin, rmax)
         _, ys, xs = _stamp_disk(grain_id, cx, cy, r, True, False)
         new = grain_id[ys, xs] < 0
-        ys, xs = ys[new], xs[new]
-        need = int(math.ceil(target - n_solid))
-        if len(ys) > need:
-            dx = np.abs(xs - cx)
-            dx = np.minimum(dx, nx - dx)
-            keep = np.argsort(dx * dx + (ys - cy) ** 2, kind="stable")[:need]
-            ys, xs = ys[keep], xs[keep]
-        grain_id[ys, xs] = gid
-        n_solid += len(ys)
+        last = False
+        if n_solid + int(new.sum()) - target > 0.005 * nx * ny:
+            lo, hi = 0.0, r  # the largest radius whose new nodes stay within the target
+            for _ in range(40):
+                mid = 0.5 * (lo + hi)
+                _, ys_, xs_ = _stamp_disk(grain_id, cx, cy, mid, True, False)
+                if n_solid + int((grain_id[ys_, xs_] < 0).sum()) <= target:
+                    lo = mid
+                else:
+                    hi = mid
+            _, ys, xs = _stamp_disk(grain_id, cx, cy, lo, True, False)
+            new = grain_id[ys, xs] < 0
+            last = True
+        grain_id[ys[new], xs[new]] = gid
+        n_solid += int(new.sum())
         gid += 1
+        if last:
+            break
     type0 = np.where(grain_id >= 0, SOLID_INERT, FLUID).astype(np.uint8)
     counts = np.bincount(grain_id[grain_id >= 0].ravel(), minlength=gid)
     order = rng.permutation(gid)
