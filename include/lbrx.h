@@ -267,8 +267,8 @@ lbrx_status lbrx_batch_step(lbrx_batch* batch, int64_t n_steps);
 /* Message for the last failure of this batch. */
 const char* lbrx_batch_last_error(const lbrx_batch* batch);
 
-/* Waits for the batch's stream and releases the batch (not the contexts).
- * NULL is a no-op. */
+/* Waits for the batch's own launches (not for work queued after them on the
+ * stream) and releases the batch (not the contexts).  NULL is a no-op. */
 lbrx_status lbrx_batch_destroy(lbrx_batch* batch);
 
 #ifdef __cplusplus

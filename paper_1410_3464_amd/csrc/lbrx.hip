@@ -2310,6 +2310,7 @@ struct lbrx_batch {
   int64_t launches = 0;  // since the table was built
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  hipEvent_t done = nullptr;  // recorded after the batch's last launch
   std::string msg;
 };
 
@@ -2398,7 +2399,13 @@ lbrx_status lbrx_batch_create(lbrx_ctx* const* ctxs, int n, lbrx_batch** out) {
   }
   std::vector<void*> inst(n);
   for (int i = 0; i < n; ++i) inst[i] = ctxs[i]->dargs;
+  if (hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
+    b->done = nullptr;
+    delete b;
+    return LBRX_E_DEVICE;
+  }
   if (!ctx_alloc(b->ctx[0], (void**)&b->dinst, n * sizeof(void*))) {
+    (void)hipEventDestroy(b->done);
     delete b;
     return LBRX_E_NOMEM;
   }
@@ -2425,26 +2432,31 @@ lbrx_status lbrx_batch_step(lbrx_batch* b, int64_t n) {
       if (s != LBRX_OK) return s;
       break;
     }
+  // every return after a launch records the batch's event (destroy waits on it)
+  auto stop = [&](lbrx_status st, const char* m) {
+    (void)hipEventRecord(b->done, b->stream);
+    return batch_err(b, st, m);
+  };
   int64_t done = 0;
   while (done < n) {
     const int lidx = (int)(b->launches % 6);
     if (lidx == 0 && n - done >= GRAPH_LEN) {
       if (!b->gexec) {
         if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
-          return batch_err(b, LBRX_E_DEVICE, "graph capture failed to start");
+          return stop(LBRX_E_DEVICE, "graph capture failed to start");
         for (int i = 0; i < GRAPH_LEN; ++i) batch_launch(b, i % 6);
         if (hipStreamEndCapture(b->stream, &b->graph) != hipSuccess ||
             hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
           batch_drop_graph(b);
-          return batch_err(b, LBRX_E_DEVICE, "graph capture failed");
+          return stop(LBRX_E_DEVICE, "graph capture failed");
         }
       }
-      if (hipGraphLaunch(b->gexec, b->stream) != hipSuccess) return batch_err(b, LBRX_E_DEVICE, "graph launch failed");
+      if (hipGraphLaunch(b->gexec, b->stream) != hipSuccess) return stop(LBRX_E_DEVICE, "graph launch failed");
       done += GRAPH_LEN;
       b->launches += GRAPH_LEN;
     } else {
       batch_launch(b, lidx);
-      if (hipGetLastError() != hipSuccess) return batch_err(b, LBRX_E_DEVICE, "batched launch failed");
+      if (hipGetLastError() != hipSuccess) return stop(LBRX_E_DEVICE, "batched launch failed");
       done += 1;
       b->launches += 1;
     }
@@ -2453,6 +2465,7 @@ lbrx_status lbrx_batch_step(lbrx_batch* b, int64_t n) {
     x->steps += n;
     x->cur = (int)(x->steps & 1);
   }
+  if (hipEventRecord(b->done, b->stream) != hipSuccess) return batch_err(b, LBRX_E_DEVICE, "event record failed");
   return LBRX_OK;
 }
 
@@ -2461,10 +2474,14 @@ const char* lbrx_batch_last_error(const lbrx_batch* b) { return b ? b->msg.c_str
 lbrx_status lbrx_batch_destroy(lbrx_batch* b) {
   if (!b) return LBRX_OK;
   (void)hipSetDevice(b->device);
-  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  // wait for the batch's own launches only (work queued after them on the
+  // stream, e.g. by another batch, keeps running)
+  if (b->done) (void)hipEventSynchronize(b->done);
+  else if (b->stream) (void)hipStreamSynchronize(b->stream);
   batch_drop_graph(b);
   ctx_free(b->ctx[0], b->dtable);
   ctx_free(b->ctx[0], b->dinst);
+  if (b->done) (void)hipEventDestroy(b->done);
   delete b;
   return LBRX_OK;
 }

@@ -81,11 +81,12 @@ def footprint_bytes(prob, precision):
 
 
 class Server:
-    def __init__(self, hbm_cap=200e9, tick=50, autotune=True, keep_fields=False):
+    def __init__(self, hbm_cap=200e9, tick=50, autotune=True, keep_fields=False, depth=2):
         self.hbm_cap = hbm_cap
         self.tick = tick
         self.autotune = autotune
         self.keep_fields = keep_fields
+        self.depth = depth  # ticks enqueued ahead of the host before it waits
 
     def run(self, requests):
         import torch
@@ -99,6 +100,13 @@ class Server:
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
         active = {}  # rid -> (request, sim, remaining, footprint)
         batches = {}  # group -> (member rids, Batch)
+        # The host runs ahead of the device by up to `depth` ticks: it waits
+        # only for the oldest tick beyond that, or for the tick in which a
+        # request finishes (its fields are read).  A batch replaced by a new
+        # membership is closed once the ticks it was launched in are done.
+        inflight = collections.deque()  # (tick, event) not yet known complete
+        retired = []  # (first tick without it, Batch)
+        tick_no, done_tick = 0, -1
         used = 0.0
         t0 = time.perf_counter()
         while pending or active:
@@ -124,7 +132,7 @@ class Server:
                 members, b = batches.get(g, ((), None))
                 if tuple(rids) != members:
                     if b is not None:
-                        b.close()
+                        retired.append((tick_no, b))
                     b = Batch([active[i][1] for i in rids])
                     batches[g] = (tuple(rids), b)
                 k = min(self.tick, min(active[i][2] for i in rids))
@@ -132,9 +140,28 @@ class Server:
                 for i in rids:
                     active[i][2] -= k
             for g in [g for g in batches if g not in groups]:
-                batches.pop(g)[1].close()
-            stream.synchronize()
-            for rid in [i for i, a in active.items() if a[2] == 0]:
+                retired.append((tick_no, batches.pop(g)[1]))
+            ev = torch.cuda.Event()
+            ev.record(stream)
+            inflight.append((tick_no, ev))
+            finished = [i for i, a in active.items() if a[2] == 0]
+            if finished:
+                ev.synchronize()
+                inflight.clear()
+                done_tick = tick_no
+            elif len(inflight) > self.depth:
+                t_, e_ = inflight.popleft()
+                e_.synchronize()
+                done_tick = t_
+            still = []
+            for t_, b_ in retired:
+                if t_ - 1 <= done_tick:
+                    b_.close()
+                else:
+                    still.append((t_, b_))
+            retired = still
+            tick_no += 1
+            for rid in finished:
                 r, sim, _, fp = active.pop(rid)
                 try:
                     sim.sync()
@@ -151,6 +178,8 @@ class Server:
                 sim.close()
         makespan = time.perf_counter() - t0
         for _, b in batches.values():
+            b.close()
+        for _, b in retired:
             b.close()
         return summarize(requests, makespan)
 
