@@ -18,6 +18,11 @@
  *  11  liquid marks for the next step (Sec. 4.5)
  *  12  push streaming with halfway bounce-back and reactive flux
  * Readings of the places where the paper is silent are stated where used.
+ * Parity unpinned (no closed form, invariant or printed value fixes them
+ * beyond conservation, which the tests check): which density each phi of
+ * Eq. 15 takes, the one-step lag of the liquid threshold's maximum
+ * density, the details of the status-change amendments of Sec. 4.5, and
+ * the time level of the velocity in the solute equilibrium.
  */
 #include "lbrx_oracle.h"
 #include <math.h>
