@@ -160,6 +160,41 @@ def batched(n_inst, steps, warmup=30, plain_warmup=5):
     }
 
 
+def precision_comparison(prob, precision, main_mlups, steps, warmup):
+    """The same lattice stepped with another storage precision (16-bit
+    deviations by default): its rate, the ratio to the main precision's and
+    its algorithmic roofline fraction."""
+    import torch
+
+    from paper_1410_3464_amd.lbrx import Lbrx
+
+    esz = {"f64": 8, "f32": 4, "f16dev": 2, "bf16dev": 2}[precision]
+    st = torch.cuda.Stream()
+    sim = Lbrx(prob, precision, stream=st.cuda_stream)
+    sim.step(warmup)
+    sim.sync()
+    b_alg, _ = algorithmic_bytes(sim.fields(), prob, esz)
+    a = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    st.synchronize()
+    t0 = time.perf_counter()
+    a.record(st)
+    sim.step(steps)
+    e.record(st)
+    st.synchronize()
+    wall = time.perf_counter() - t0
+    sim.sync()
+    kern_ms = a.elapsed_time(e) / steps
+    sim.close()
+    mlups = prob.nx * prob.ny * steps / wall / 1e6
+    print(f"# {precision}: {mlups:.1f} MLUPS", file=sys.stderr, flush=True)
+    return {"dtype": precision, "value": round(mlups, 1), "unit": "MLUPS",
+            "ms_per_step": round(wall / steps * 1e3, 4), "ratio_to_main": round(mlups / main_mlups, 3),
+            "roofline_frac": round(b_alg / (kern_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+            "traffic": None if measured_traffic(precision, prob.nx) is None
+            else round(measured_traffic(precision, prob.nx) / 1e9, 4)}
+
+
 def cpu_baseline(prob, steps):
     """The FP64 oracle, as it stands, single-threaded on the host: `steps` steps of
     the same lattice."""
@@ -190,6 +225,8 @@ def main():
     ap.add_argument("--batch-instances", type=int, default=256,
                     help="instances of the many-simulations comparison (0: skip it)")
     ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--compare-precision", default="f16dev",
+                    help="storage precision timed on the same lattice beside the main one ('' skips it)")
     ap.add_argument("--copy-probe-gb", type=float, default=0.0,
                     help="run a plain device-to-device copy of this many GB first (counter calibration)")
     args = ap.parse_args()
@@ -292,6 +329,8 @@ def main():
     }
     sim.close()
     del sim
+    if args.compare_precision and args.compare_precision != args.precision:
+        out["precision"] = precision_comparison(prob, args.compare_precision, mlups, args.steps, args.warmup)
     if args.batch_instances > 0:
         out["batched"] = batched(args.batch_instances, args.batch_steps)
     if args.serve_requests > 0:
