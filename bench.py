@@ -102,7 +102,7 @@ def serving(n, interarrival):
     }
 
 
-def batched(n_inst, steps, warmup=30, plain_warmup=5):
+def batched(n_inst, steps, warmup=30, plain_warmup=30):
     """Many independent simulations: n_inst FP32 instances of the porous-medium
     generator (square sides log-uniform in 64-1024, porosity uniform in
     0.4-0.8, rate constants log-uniform in 1e-6-1e-1), advanced together by one

@@ -1456,6 +1456,10 @@ __global__ __launch_bounds__(LSUM_THREADS) void k_ledger_sum(const double* led, 
 
 // ---------------------------------------------------------------- host side
 constexpr int SEG_ROWS = 12;  // default rows per item (LBRX_SEG_ROWS overrides, 1..HMAX)
+// Steps per captured HIP graph of launches: a multiple of 6, the period of
+// the step phases (buffer parity and rho_max slot), so that one graph serves
+// every replay that starts at a step count divisible by 6.
+constexpr int GRAPH_LEN = 30;
 
 template <typename T> using KFnT = void (*)(const LaunchArgs);
 
@@ -1514,6 +1518,8 @@ struct lbrx_ctx {
   void* (*dev_alloc)(uint64_t, void*) = nullptr;  // caller's device allocator (else hipMalloc)
   void (*dev_free)(void*, void*) = nullptr;
   void* alloc_user = nullptr;
+  hipGraph_t graph = nullptr;  // GRAPH_LEN single launches, captured on first use
+  hipGraphExec_t gexec = nullptr;
 };
 
 namespace {
@@ -2079,9 +2085,41 @@ lbrx_status lbrx_step(lbrx_ctx* x, int64_t n) {
   if (x->failed) return set_err(x, LBRX_E_STATE, "context failed earlier: " + x->msg);
   if (n < 0) return set_err(x, LBRX_E_INVAL, "n_steps must be >= 0");
   HIPCHK(x, hipSetDevice(x->device));
-  for (int64_t i = 0; i < n; ++i) {
-    const lbrx_status s = launch_step(x);
-    if (s != LBRX_OK) return s;
+  // a stream the caller is capturing gets plain launches (they become part
+  // of the caller's graph)
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  HIPCHK(x, hipStreamIsCapturing(x->stream, &cap));
+  const bool graphs = cap == hipStreamCaptureStatusNone;
+  int64_t done = 0;
+  while (done < n) {
+    // runs of GRAPH_LEN steps starting at a step count divisible by 6 (the
+    // period of the step phases) replay one captured graph of single launches
+    if (graphs && x->steps % 6 == 0 && n - done >= GRAPH_LEN) {
+      if (!x->gexec) {
+        const int64_t s0 = x->steps;
+        HIPCHK(x, hipStreamBeginCapture(x->stream, hipStreamCaptureModeThreadLocal));
+        for (int i = 0; i < GRAPH_LEN; ++i) {
+          launch_one(x, false);
+          x->steps += 1;
+        }
+        x->steps = s0;
+        const hipError_t e = hipStreamEndCapture(x->stream, &x->graph);
+        if (e != hipSuccess || hipGraphInstantiate(&x->gexec, x->graph, nullptr, nullptr, 0) != hipSuccess) {
+          if (x->graph) (void)hipGraphDestroy(x->graph);
+          x->graph = nullptr;
+          x->gexec = nullptr;
+          return set_err(x, LBRX_E_DEVICE, "graph capture failed");
+        }
+      }
+      HIPCHK(x, hipGraphLaunch(x->gexec, x->stream));
+      x->steps += GRAPH_LEN;
+      x->cur = (int)(x->steps & 1);
+      done += GRAPH_LEN;
+    } else {
+      const lbrx_status s = launch_step(x);
+      if (s != LBRX_OK) return s;
+      done += 1;
+    }
   }
   return LBRX_OK;
 }
@@ -2295,9 +2333,7 @@ int64_t lbrx_step_count(const lbrx_ctx* x) { return x ? x->steps : -1; }
 // Several simulations stepped by one launch per step: the workgroups of all
 // of them in one grid, each looking up its simulation, item block and step
 // phase in a table built on the host.  Runs of GRAPH_LEN steps replay a
-// captured HIP graph (GRAPH_LEN is a multiple of 6, the period of the phases,
-// so one graph serves every replay).
-constexpr int GRAPH_LEN = 30;
+// captured HIP graph.
 
 struct lbrx_batch {
   std::vector<lbrx_ctx*> ctx;
@@ -2494,6 +2530,8 @@ lbrx_status lbrx_destroy(lbrx_ctx* x) {
   if (!x) return LBRX_OK;
   (void)hipSetDevice(x->device);
   if (x->stream) (void)hipStreamSynchronize(x->stream);
+  if (x->gexec) (void)hipGraphExecDestroy(x->gexec);
+  if (x->graph) (void)hipGraphDestroy(x->graph);
   for (int i = 0; i < 2; ++i) {
     ctx_free(x, x->f[i]);
     ctx_free(x, x->g[i]);
