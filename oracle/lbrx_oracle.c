@@ -72,6 +72,11 @@ struct orc_sim {
   char err[256];
 };
 
+/* Neighbour of (x, y) in direction a; -1 outside a wall side.  Beyond a free
+ * outlet (Sec. 5.1: zero gradient of every variable) lies a ghost row that
+ * repeats the top row, so the neighbour there is the top-row node of the
+ * same column: its type, potentials, concentrations and post-collision
+ * populations stand for the ghost's. */
 static int nb(const orc_sim* s, int x, int y, int a) {
   int X = x + EX[a], Y = y + EY[a];
   const int nx = s->p.nx, ny = s->p.ny;
@@ -79,11 +84,18 @@ static int nb(const orc_sim* s, int x, int y, int a) {
     if (!s->p.periodic_x) return -1;
     X = (X + nx) % nx;
   }
-  if (Y < 0 || Y >= ny) {
+  if (Y >= ny && s->p.outlet_top) {
+    Y = ny - 1;
+  } else if (Y < 0 || Y >= ny) {
     if (!s->p.periodic_y) return -1;
     Y = (Y + ny) % ny;
   }
   return Y * nx + X;
+}
+
+/* 1 if the link from (x, y) in direction a crosses the free outlet */
+static int crosses_outlet(const orc_sim* s, int y, int a) {
+  return s->p.outlet_top && y + EY[a] >= s->p.ny;
 }
 
 static void* xcalloc(size_t n, size_t sz) {
@@ -135,6 +147,7 @@ static int validate(const orc_params* p, char* err, int errlen) {
     if (!(p->het_k[r] >= 0.0)) return fail(err, errlen, "rate constants must be >= 0");
   }
   if (!(p->liquid_frac >= 0.0 && p->liquid_frac < 1.0)) return fail(err, errlen, "liquid_frac in [0,1)");
+  if (p->outlet_top && (p->periodic_y || p->ny < 2)) return fail(err, errlen, "a free outlet needs walls in y and ny >= 2");
   return 1;
 }
 
@@ -427,7 +440,7 @@ static int macros(orc_sim* s) {
 
 int orc_step(orc_sim* s, int nsteps) {
   const orc_params* p = &s->p;
-  const int N = s->N, ns = s->ns, nx = p->nx;
+  const int N = s->N, ns = s->ns, nx = p->nx, ny = p->ny;
   for (int it = 0; it < nsteps; ++it) {
     if (macros(s) != 0) return -1;
 
@@ -687,16 +700,32 @@ int orc_step(orc_sim* s, int nsteps) {
      * step.  Flow: halfway bounce-back off any non-fluid neighbour or
      * non-periodic boundary.  Solute: the liquid set only; bounce-back off gas
      * (the no-flux liquid-gas interface of Eq. 26) and solid, minus the
-     * reactant's link flux and plus the product's on reactive solid. */
+     * reactant's link flux and plus the product's on reactive solid.
+     * Free outlet: a population sent into a fluid (liquid) ghost node leaves
+     * the lattice, and the ghost row sends the top row what its model node
+     * sends the row below it. */
     for (int sg = 0; sg < 2; ++sg)
       for (int a = 0; a < 9; ++a)
         for (int i = 0; i < N; ++i) {
           if (s->type[i] != ORC_FLUID) continue;
           const int j = nb(s, i % nx, i / nx, a);
           const double v = s->fs[(sg * 9 + a) * N + i];
-          if (j >= 0 && s->type[j] == ORC_FLUID) s->fn[(sg * 9 + a) * N + j] = v;
-          else s->fn[(sg * 9 + OPP[a]) * N + i] = v;
+          if (j >= 0 && s->type[j] == ORC_FLUID) {
+            if (!crosses_outlet(s, i / nx, a)) s->fn[(sg * 9 + a) * N + j] = v;
+          } else {
+            s->fn[(sg * 9 + OPP[a]) * N + i] = v;
+          }
         }
+    if (p->outlet_top)
+      for (int i = (ny - 1) * nx; i < N; ++i) {
+        if (s->type[i] != ORC_FLUID) continue;
+        for (int a = 1; a < 9; ++a) {
+          if (EY[a] >= 0) continue;
+          const int j = nb(s, i % nx, ny - 1, OPP[a]);  /* the ghost sender's model node */
+          if (j < 0 || s->type[j] != ORC_FLUID) continue;  /* bounced back above */
+          for (int sg = 0; sg < 2; ++sg) s->fn[(sg * 9 + a) * N + i] = s->fs[(sg * 9 + a) * N + j];
+        }
+      }
     for (int k = 0; k < ns; ++k)
       for (int a = 0; a < 5; ++a)
         for (int i = 0; i < N; ++i) {
@@ -704,7 +733,7 @@ int orc_step(orc_sim* s, int nsteps) {
           const int j = nb(s, i % nx, i / nx, a);
           double v = s->gs[(k * 5 + a) * N + i];
           if (j >= 0 && s->liq[j]) {
-            s->gn[(k * 5 + a) * N + j] = v;
+            if (!crosses_outlet(s, i / nx, a)) s->gn[(k * 5 + a) * N + j] = v;
             continue;
           }
           if (j >= 0 && (s->type[j] == ORC_SOLID_D || s->type[j] == ORC_SOLID_F)) {
@@ -722,6 +751,12 @@ int orc_step(orc_sim* s, int nsteps) {
           }
           s->gn[(k * 5 + OPP[a]) * N + i] = v;
         }
+    if (p->outlet_top)
+      for (int i = (ny - 1) * nx; i < N; ++i) {
+        if (!s->liq[i]) continue;
+        /* D2Q5: the ghost above a top node models the node itself */
+        for (int k = 0; k < ns; ++k) s->gn[(k * 5 + 4) * N + i] = s->gs[(k * 5 + 4) * N + i];
+      }
     for (int i = 0; i < N; ++i) {
       if (!(s->type[i] != ORC_FLUID && s->tnext[i] == ORC_FLUID)) continue;
       for (int sg = 0; sg < 2; ++sg)

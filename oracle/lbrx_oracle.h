@@ -69,6 +69,8 @@ typedef struct {
   double het_k[ORC_MAX_RXN];
   double het_Ceq[ORC_MAX_RXN];
   double het_mvol[ORC_MAX_RXN];      /* molar volume x specific area per link */
+  int32_t outlet_top;     /* 1: the side beyond y = ny - 1 is a free outlet with zero
+                             gradient of every variable (Sec. 5.1); needs periodic_y = 0 */
 } orc_params;
 
 /* cumulative balance ledger, all FP64 */

@@ -37,6 +37,7 @@ class _Params(C.Structure):
         ("n_het", C.c_int32), ("het_reactant", C.c_int32 * MAXR), ("het_product", C.c_int32 * MAXR),
         ("het_surface", C.c_int32 * MAXR), ("het_mode", C.c_int32 * MAXR), ("het_irrev", C.c_int32 * MAXR),
         ("het_k", C.c_double * MAXR), ("het_Ceq", C.c_double * MAXR), ("het_mvol", C.c_double * MAXR),
+        ("outlet_top", C.c_int32),
     ]
 
 
@@ -126,6 +127,7 @@ def _params(prob, psi_literal=False):
         p.het_mode[i] = _HET_MODE[r.mode]
         p.het_irrev[i] = int(r.irreversible)
         p.het_k[i], p.het_Ceq[i], p.het_mvol[i] = r.k, r.C_eq, r.molar_volume
+    p.outlet_top = int(prob.outlet_top)
     return p
 
 

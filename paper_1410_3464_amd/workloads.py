@@ -92,6 +92,7 @@ class Problem:
     ny: int
     periodic_x: bool
     periodic_y: bool
+    outlet_top: bool = False  # the side beyond y = ny - 1 is a zero-gradient free outlet (Sec. 5.1)
     tau: tuple = (1.0, 1.0)
     w_adh: tuple = (0.0, 0.0)
     gbody: tuple = (0.0, 0.0)
