@@ -93,6 +93,14 @@ static int nb(const orc_sim* s, int x, int y, int a) {
   return Y * nx + X;
 }
 
+/* Neighbour for the amendments of Sec. 4.5, which move content between
+ * lattice nodes only: as nb(), but -1 beyond the free outlet (a ghost node
+ * neither gives, takes nor counts). */
+static int nb_node(const orc_sim* s, int x, int y, int a) {
+  if (s->p.outlet_top && y + EY[a] >= s->p.ny) return -1;
+  return nb(s, x, y, a);
+}
+
 /* 1 if the link from (x, y) in direction a crosses the free outlet */
 static int crosses_outlet(const orc_sim* s, int y, int a) {
   return s->p.outlet_top && y + EY[a] >= s->p.ny;
@@ -567,7 +575,7 @@ int orc_step(orc_sim* s, int nsteps) {
         if (s->V[i] <= 0.0) {
           int nf = 0;
           for (int a = 1; a < 9; ++a) {
-            const int j = nb(s, x, y, a);
+            const int j = nb_node(s, x, y, a);
             if (j >= 0 && s->type[j] == ORC_FLUID) ++nf;
           }
           if (nf > 0) s->tnext[i] = ORC_FLUID;
@@ -612,11 +620,11 @@ int orc_step(orc_sim* s, int nsteps) {
       if (s->type[i] == ORC_FLUID) {
         double don[2] = {0.0, 0.0};
         for (int a = 1; a < 9; ++a) {
-          const int j = nb(s, x, y, a);
+          const int j = nb_node(s, x, y, a);
           if (j < 0 || !s->stranded[j]) continue;
           int m = 0;
           for (int b = 1; b < 9; ++b) {
-            const int q = nb(s, j % nx, j / nx, b);
+            const int q = nb_node(s, j % nx, j / nx, b);
             if (q >= 0 && s->type[q] == ORC_FLUID) ++m;
           }
           for (int sg = 0; sg < 2; ++sg) don[sg] += s->rho[sg * N + j] / m;
@@ -629,11 +637,11 @@ int orc_step(orc_sim* s, int nsteps) {
         double donk[ORC_MAX_SPECIES] = {0};
         int any = 0;
         for (int a = 1; a < 5; ++a) {
-          const int j = nb(s, x, y, a);
+          const int j = nb_node(s, x, y, a);
           if (j < 0 || !(s->liqprev[j] && !s->liq[j])) continue;
           int m = 0;
           for (int b = 1; b < 5; ++b) {
-            const int q = nb(s, j % nx, j / nx, b);
+            const int q = nb_node(s, j % nx, j / nx, b);
             if (q >= 0 && s->liq[q]) ++m;
           }
           for (int k = 0; k < ns; ++k) donk[k] += s->C[k * N + j] / m;
@@ -650,7 +658,7 @@ int orc_step(orc_sim* s, int nsteps) {
       if (s->stranded[i]) {
         int m = 0;
         for (int b = 1; b < 9; ++b) {
-          const int q = nb(s, x, y, b);
+          const int q = nb_node(s, x, y, b);
           if (q >= 0 && s->type[q] == ORC_FLUID) ++m;
         }
         if (m == 0)
@@ -659,7 +667,7 @@ int orc_step(orc_sim* s, int nsteps) {
       if (s->liqprev[i] && !s->liq[i]) {
         int m = 0;
         for (int b = 1; b < 5; ++b) {
-          const int q = nb(s, x, y, b);
+          const int q = nb_node(s, x, y, b);
           if (q >= 0 && s->liq[q]) ++m;
         }
         if (m == 0)
@@ -676,7 +684,7 @@ int orc_step(orc_sim* s, int nsteps) {
       double sum[2] = {0.0, 0.0};
       int m = 0;
       for (int a = 1; a < 9; ++a) {
-        const int j = nb(s, x, y, a);
+        const int j = nb_node(s, x, y, a);
         if (j < 0 || s->type[j] != ORC_FLUID) continue;
         sum[0] += s->rho[j];
         sum[1] += s->rho[N + j];
