@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define LBRX_ABI_VERSION 4u
+#define LBRX_ABI_VERSION 5u
 #define LBRX_MAX_SPECIES 8
 #define LBRX_MAX_RXN 8
 
@@ -109,7 +109,13 @@ typedef struct {
   uint32_t abi_version;  /* must be LBRX_ABI_VERSION */
   int32_t nx, ny;        /* lattice size, each >= 3 */
   uint32_t periodic;     /* bit 0: x periodic, bit 1: y periodic; a non-periodic
-                            side is a halfway bounce-back wall just outside the domain */
+                            side is a halfway bounce-back wall just outside the domain,
+                            except that bit 2 makes the side beyond y = ny - 1 a free
+                            outlet with zero gradient of every variable (Sec. 5.1): a
+                            ghost row repeating the top row's type, potentials,
+                            concentrations and post-collision populations.  Bit 2
+                            needs bit 1 clear, ny >= 2 and FP64 or FP32 storage
+                            (LBRX_E_INVAL otherwise); other bits must be clear */
   int32_t precision;     /* lbrx_precision */
   double tau[2];         /* flow relaxation times, > 1/2 (Eq. 6, 10) */
   double w_adh[2];       /* fluid-solid interaction strengths (Eq. 16) */

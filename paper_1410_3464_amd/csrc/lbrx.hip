@@ -199,6 +199,15 @@ __device__ inline bool wrap(int& X, int n, int per) {
   return true;
 }
 
+// Row Y with a free outlet beyond row n - 1 (a wall below row 0): the ghost
+// rows beyond the outlet repeat row n - 1 (zero gradient of every variable,
+// Sec. 5.1), so such a row becomes n - 1.
+__device__ inline bool wrap_out(int& Y, int n) {
+  if (Y < 0) return false;
+  if (Y >= n) Y = n - 1;
+  return true;
+}
+
 template <typename T> __device__ inline T dexp(T x);
 template <> __device__ inline double dexp<double>(double x) { return exp(x); }
 template <> __device__ inline float dexp<float>(float x) { return __expf(x); }
@@ -317,7 +326,10 @@ template <typename T> __device__ inline uint32_t flags_of(T v) {
 
 // Population storage: the working precision itself, or 16-bit deviations
 // (FP16 or BF16, with FP32 arithmetic) from the coded references above.
-enum { SM_PLAIN = 0, SM_F16 = 1, SM_BF16 = 2 };
+// SM_OUT: plain storage, kernels built with the free-outlet rows (a separate
+// instantiation, so that the other kernels carry none of its code)
+enum { SM_PLAIN = 0, SM_F16 = 1, SM_BF16 = 2, SM_OUT = 3 };
+__host__ __device__ constexpr bool sm_dev(int sm) { return sm == SM_F16 || sm == SM_BF16; }
 template <typename T, int SM> struct StoreT { using type = T; };
 template <> struct StoreT<float, SM_F16> { using type = uint16_t; };
 template <> struct StoreT<float, SM_BF16> { using type = uint16_t; };
@@ -338,8 +350,8 @@ template <typename T> struct alignas(2 * sizeof(T)) RF {
 
 template <typename T, int NS, int SM> struct WaveLds {
   static constexpr int NSA = NS > 0 ? NS : 1;
-  static constexpr int NRF = SM != SM_PLAIN ? 3 : 1;  // reference rows (16-bit storage only)
-  static constexpr int NHF = SM != SM_PLAIN ? 2 : 1;
+  static constexpr int NRF = sm_dev(SM) ? 3 : 1;  // reference rows (16-bit storage only)
+  static constexpr int NHF = sm_dev(SM) ? 2 : 1;
   // ring rows (R - 1, R, R + 1 in rotation) x columns x0 - 1 .. x0 + 64
   PQ<T> pq[3][SW + 2];
   T r1[3][SW + 2], r2[3][SW + 2];
@@ -496,7 +508,10 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
   constexpr int NSA = NS > 0 ? NS : 1;
   using ST = typename StoreT<T, SM>::type;  // stored population type
   constexpr unsigned ES = sizeof(ST);
-  constexpr bool DEV = SM != SM_PLAIN;
+  constexpr bool DEV = sm_dev(SM);
+  // this simulation's top side is a free outlet (only in SM_OUT kernels; a
+  // batch of mixed simulations runs them all in one)
+  const bool outy = SM == SM_OUT && A.c.per_y == 2;
   static_assert(!DEV || std::is_same<T, float>::value, "16-bit storage computes in FP32");
   const KAS KConst& c = A.c;
   const KAS KT<T>& k = A.k;
@@ -511,6 +526,9 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
   const int y1 = min(y0 + c.seg_rows, c.ny);
   const int nrow = y1 - y0;
   const int nx = c.nx, ny = c.ny;
+  // a row coordinate inside the lattice, or a ghost row of the free outlet
+  // (as the row it repeats), or "outside"
+  auto wrap_y = [&](int& Y) -> bool { return outy ? wrap_out(Y, ny) : wrap(Y, ny, c.per_y); };
   const unsigned upitch = (unsigned)c.pitch;
   constexpr unsigned PE = 2 * ES;      // bytes per flow slot (a pair)
   const unsigned PS = upitch * PE;     // bytes per flow slot plane row
@@ -540,7 +558,7 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
 
   // status word of node (X, Y), TB_WALL outside a non-periodic side
   auto word_at = [&](int X, int Y) -> uint32_t {
-    if (wrap(X, nx, c.per_x) && wrap(Y, ny, c.per_y)) return bload<uint32_t>(rt, (unsigned)X * 4u, (unsigned)Y * upitch * 4u);
+    if (wrap(X, nx, c.per_x) && wrap_y(Y)) return bload<uint32_t>(rt, (unsigned)X * 4u, (unsigned)Y * upitch * 4u);
     return TB_WALL;
   };
 
@@ -550,9 +568,11 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
   // wall.  co[] are the byte offsets of columns x-1, x, x+1 (wrapped); Yw is
   // the wrapped row of an in-domain node.
   auto pull = [&](const unsigned (&co)[3], int Yw, uint32_t w, bool validf, bool liqp, T(&f)[2][9], T(&g)[NSA][5]) {
+    // (beyond a wall the neighbour bit is clear and the row is never read;
+    // beyond the outlet the ghost row is row ny - 1 itself)
     int ym = Yw - 1, yp = Yw + 1;
     if (ym < 0) ym += ny;
-    if (yp >= ny) yp -= ny;
+    if (yp >= ny) yp = outy ? ny - 1 : yp - ny;
     const unsigned ur[3] = {(unsigned)ym, (unsigned)Yw, (unsigned)yp};
     // a stored value becomes a population: itself, or (16-bit storage)
     // deviation / scale + weight x this node's reference
@@ -626,11 +646,18 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
         }
       };
       gin(0, own);
+      // On the top row at a free outlet the ghost row above sends slot 2, not
+      // slot 4, of the node itself: the writer keeps its post-collision
+      // population 4 there (slot 4 may carry a reactive bounce-back).  The
+      // shift is zero in every other kernel, which keeps their address
+      // arithmetic (and load schedule) as it is.
+      const bool gtop = outy && Yw == ny - 1;
 #pragma unroll
       for (int b = 1; b < 5; ++b) {
         const int a = opp(b);
         const bool src = (w >> (NBL_SHIFT + b - 1)) & 1u;
-        gin(a, src ? (co[ex(b) + 1] << GSH) + (ur[ey(b) + 1] * RSG + (unsigned)a * PSG) : own + (unsigned)b * PSG);
+        const unsigned sh = (b == 2 && gtop) ? 2u * PSG : 0u;
+        gin(a, src ? (co[ex(b) + 1] << GSH) + (ur[ey(b) + 1] * RSG + (unsigned)a * PSG - sh) : own + (unsigned)b * PSG);
       }
     }
   };
@@ -704,7 +731,7 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
     const int hs = lane >> 5, hr = lane & 31;
     const bool hact = hr < nrow + 2;
     int HX = hs ? x0 + SW : x0 - 1, HY = y0 - 1 + hr;
-    const bool indom = hact && wrap(HX, nx, c.per_x) && wrap(HY, ny, c.per_y);
+    const bool indom = hact && wrap(HX, nx, c.per_x) && wrap_y(HY);
     const uint32_t hw = indom ? bload<uint32_t>(rt, (unsigned)HX * 4u, (unsigned)HY * upitch * 4u) : (uint32_t)TB_WALL;
     const int t = (int)(hw & TB_T);
     const bool fluid = indom && t == T_FLUID;
@@ -766,7 +793,7 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
   Mom<T, NS> mc;
   // status word of this lane's column in row Y (the column is wrapped once)
   auto word_row = [&](int Y) -> uint32_t {
-    if (colin && wrap(Y, ny, c.per_y)) return bload<uint32_t>(rt, (unsigned)Xw * 4u, (unsigned)Y * upitch * 4u);
+    if (colin && wrap_y(Y)) return bload<uint32_t>(rt, (unsigned)Xw * 4u, (unsigned)Y * upitch * 4u);
     return TB_WALL;
   };
   uint32_t w_cur = 0, w_next = word_row(y0 - 1);
@@ -779,7 +806,7 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
     {
       // ---------------------------------------------------- phase 1, row R + 1
       int Yw = Rn;
-      const bool rowin = wrap(Yw, ny, c.per_y);
+      const bool rowin = wrap_y(Yw);
       const bool indom = colin && rowin;
       const uint32_t w = w_next;
       const int t = (int)(w & TB_T);
@@ -850,8 +877,15 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
         nq[a] = L.pq[slot(ey(a))][lane + 1 + ex(a)];
         nt[a] = flags_of<T>(nq[a].fl);
       }
+      // The amendments of Sec. 4.5 move content between lattice nodes only:
+      // beyond the free outlet there is no node to give, take or be counted,
+      // so their neighbour flags (am) see a wall there; transport and forces
+      // (nt) see the ghost row.
+      const bool top_out = outy && R == ny - 1;
+      auto am = [&](int a) -> uint32_t { return (top_out && ey(a) > 0) ? (uint32_t)TB_WALL : nt[a]; };
       // node flags two links away (rare amendment paths)
       auto far_flags = [&](int dx, int dy) -> uint32_t {
+        if (outy && R + dy >= ny) return TB_WALL;
         const uint32_t v = word_at(X + dx, R + dy);
         return (v & TB_WALL) ? (uint32_t)TB_WALL : flags_w(v);
       };
@@ -1013,7 +1047,7 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
             T don[2] = {T(0), T(0)};
 #pragma unroll
             for (int a = 1; a < 9; ++a) {
-              if (!(nt[a] & TB_WALL) && (nt[a] & TB_STR)) {
+              if (!(am(a) & TB_WALL) && (am(a) & TB_STR)) {
                 int mm = 0;
 #pragma unroll 1
                 for (int b = 1; b < 9; ++b) mm += is_fluid(far_flags(ex(a) + ex(b), ey(a) + ey(b))) ? 1 : 0;
@@ -1070,7 +1104,7 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
               for (int kk = 0; kk < NSA; ++kk) donk[kk] = T(0);
 #pragma unroll
               for (int a = 1; a < 5; ++a) {
-                if (!(nt[a] & TB_WALL) && (nt[a] & TB_LIQP) && !(nt[a] & LF_LIQN)) {
+                if (!(am(a) & TB_WALL) && (am(a) & TB_LIQP) && !(am(a) & LF_LIQN)) {
                   int mm = 0;
 #pragma unroll 1
                   for (int b = 1; b < 5; ++b) mm += is_liq(far_flags(ex(a) + ex(b), ey(a) + ey(b))) ? 1 : 0;
@@ -1088,6 +1122,14 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
             // reactive solid comes back next step minus the reactant's (plus the
             // product's) link flux; the node also collects the precipitate of GROWS
             // reactions (Eq. 35)
+            // Free outlet: the ghost row above a top-row node sends it that
+            // node's post-collision population 4, which slot 4 may not keep (a
+            // reactive link below bounces it back with its flux); slot 2 heads
+            // out through the outlet and is read by nobody, so it keeps the copy.
+            if (top_out) {
+#pragma unroll
+              for (int kk = 0; kk < NSA; ++kk) g[kk][2] = g[kk][4];
+            }
             bool any_rs = false;
 #pragma unroll
             for (int a = 1; a < 5; ++a) any_rs |= is_rsolid(nt[a]);
@@ -1183,7 +1225,7 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
             T sum0 = T(0), sum1 = T(0);
 #pragma unroll
             for (int a = 1; a < 9; ++a) {
-              if (!is_fluid(nt[a])) continue;
+              if (!is_fluid(am(a))) continue;
               const int sl = slot(ey(a)), lx = lane + 1 + ex(a);
               sum0 += L.r1[sl][lx];
               sum1 += L.r2[sl][lx];
@@ -1217,7 +1259,7 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
           if (w & TB_STR) {
             int mm = 0;
 #pragma unroll
-            for (int b = 1; b < 9; ++b) mm += is_fluid(nt[b]) ? 1 : 0;
+            for (int b = 1; b < 9; ++b) mm += is_fluid(am(b)) ? 1 : 0;
             if (mm == 0) {
               atomicAdd(&L.rare[2], (double)m.rho[0]);
               atomicAdd(&L.rare[3], (double)m.rho[1]);
@@ -1228,7 +1270,7 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
         if (liqp && !liq) {
           int mm = 0;
 #pragma unroll
-          for (int b = 1; b < 5; ++b) mm += is_liq(nt[b]) ? 1 : 0;
+          for (int b = 1; b < 5; ++b) mm += is_liq(am(b)) ? 1 : 0;
           if (mm == 0) {
 #pragma unroll
             for (int kk = 0; kk < NS; ++kk) atomicAdd(&L.rare[8 + kk], (double)m.C[kk]);
@@ -1560,6 +1602,13 @@ std::string validate(const lbrx_params* p) {
   if (!p) return "params is NULL";
   if (p->abi_version != LBRX_ABI_VERSION) return "abi_version mismatch";
   if (p->nx < 1 || p->ny < 1) return "nx and ny must be >= 1";
+  if (p->periodic & ~7u) return "unknown bits in periodic";
+  if ((p->periodic & 4u) && ((p->periodic & 2u) || p->ny < 2)) return "a free outlet needs walls in y and ny >= 2";
+  // A 16-bit population is a deviation from the reference of the one node
+  // that pulls it; beyond the outlet the top row's downward populations have
+  // two readers (the row below, and the top row through the ghost row).
+  if ((p->periodic & 4u) && (p->precision == LBRX_F16DEV || p->precision == LBRX_BF16DEV))
+    return "a free outlet needs FP64 or FP32 storage";
   if (p->seg_rows < 0 || p->seg_rows > HMAX) return "seg_rows must lie in 0..30";
   if ((long long)p->nx * p->ny > (1ll << 31) - 1) return "lattice too large";
   if (p->precision != LBRX_F64 && p->precision != LBRX_F32 && p->precision != LBRX_F16DEV &&
@@ -1909,7 +1958,7 @@ lbrx_status lbrx_create(const lbrx_params* p, void* hip_stream, lbrx_ctx** out) 
   c.ny = p->ny;
   c.pitch = (p->nx + 63) / 64 * 64;
   c.per_x = (p->periodic & 1u) ? 1 : 0;
-  c.per_y = (p->periodic & 2u) ? 1 : 0;
+  c.per_y = (p->periodic & 2u) ? 1 : ((p->periodic & 4u) ? 2 : 0);
   c.plane = (long long)c.pitch * p->ny;
   c.ns = p->n_species;
   x->precision = p->precision;
@@ -1928,7 +1977,7 @@ lbrx_status lbrx_create(const lbrx_params* p, void* hip_stream, lbrx_ctx** out) 
   c.gbytes = (unsigned)(g_elems(c) * x->esz);
   c.tbytes = (unsigned)((unsigned long long)c.plane * 4ull);
   const int sm = storage_mode(p->precision);
-  c.ncw = (sm != SM_PLAIN && c.ns > 0) ? (c.ns + 3) / 4 : 0;
+  c.ncw = (sm_dev(sm) && c.ns > 0) ? (c.ns + 3) / 4 : 0;
   c.cbytes = (unsigned)((unsigned long long)(c.ncw > 0 ? c.ncw : 1) * c.plane * 4ull);
   for (int s = 0; s < 2; ++s) {
     c.tau[s] = p->tau[s];
@@ -1989,13 +2038,16 @@ lbrx_status lbrx_create(const lbrx_params* p, void* hip_stream, lbrx_ctx** out) 
   }
   fill_kt(x->kd, p, c, D);
   fill_kt(x->kf, p, c, D);
-  if (sm != SM_PLAIN) fill_dev_constants(x->kf, p, c);
-  x->step64 = pick<double, SM_PLAIN, false>(c.ns);
-  x->export64 = pick<double, SM_PLAIN, true>(c.ns);
+  if (sm_dev(sm)) fill_dev_constants(x->kf, p, c);
+  const bool outlet = c.per_y == 2;  // free outlet: the SM_OUT kernels (plain storage only)
+  x->step64 = outlet ? pick<double, SM_OUT, false>(c.ns) : pick<double, SM_PLAIN, false>(c.ns);
+  x->export64 = outlet ? pick<double, SM_OUT, true>(c.ns) : pick<double, SM_PLAIN, true>(c.ns);
   x->step32 = sm == SM_F16 ? pick<float, SM_F16, false>(c.ns)
-             : sm == SM_BF16 ? pick<float, SM_BF16, false>(c.ns) : pick<float, SM_PLAIN, false>(c.ns);
+             : sm == SM_BF16 ? pick<float, SM_BF16, false>(c.ns)
+             : outlet ? pick<float, SM_OUT, false>(c.ns) : pick<float, SM_PLAIN, false>(c.ns);
   x->export32 = sm == SM_F16 ? pick<float, SM_F16, true>(c.ns)
-               : sm == SM_BF16 ? pick<float, SM_BF16, true>(c.ns) : pick<float, SM_PLAIN, true>(c.ns);
+               : sm == SM_BF16 ? pick<float, SM_BF16, true>(c.ns)
+               : outlet ? pick<float, SM_OUT, true>(c.ns) : pick<float, SM_PLAIN, true>(c.ns);
 
   auto fail = [&](lbrx_status s, const std::string& m) {
     g_create_err = m;
@@ -2398,7 +2450,10 @@ void batch_launch(lbrx_batch* b, int lidx) {
   L.ninst = (int)b->ctx.size();
   L.launch = lidx;
   const dim3 grid(b->nblocks), block(64, WPB);
+  // the kernels of a simulation with a free outlet also run the others
   lbrx_ctx* x = b->ctx[0];
+  for (lbrx_ctx* y : b->ctx)
+    if (y->c.per_y == 2) x = y;
   if (b->precision == LBRX_F64)
     hipLaunchKernelGGL(x->step64, grid, block, 0, b->stream, L);
   else

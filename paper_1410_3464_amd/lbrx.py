@@ -14,7 +14,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbrx.so")
 
-ABI_VERSION = 4
+ABI_VERSION = 5
 MAXS = 8
 MAXR = 8
 F64, F32, F16DEV, BF16DEV = 0, 1, 2, 3
@@ -158,7 +158,7 @@ def make_params(prob, precision="f64", seg_rows=0):
     p.abi_version = ABI_VERSION
     p.seg_rows = int(seg_rows)
     p.nx, p.ny = prob.nx, prob.ny
-    p.periodic = (1 if prob.periodic_x else 0) | (2 if prob.periodic_y else 0)
+    p.periodic = (1 if prob.periodic_x else 0) | (2 if prob.periodic_y else 0) | (4 if prob.outlet_top else 0)
     p.precision = _PREC[precision]
     p.tau[:] = list(prob.tau)
     p.w_adh[:] = list(prob.w_adh)

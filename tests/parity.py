@@ -11,6 +11,8 @@ import dataclasses
 
 import numpy as np
 
+from paper_1410_3464_amd import workloads as W
+
 FIELDS = ("rho1", "rho2", "ux", "uy", "V")
 
 
@@ -87,3 +89,23 @@ def species_variant(prob, ns):
             if ok((r.reactant + off, rp)):
                 het.append(dataclasses.replace(r, reactant=r.reactant + off, product=rp))
     return prob.copy(species=sp, C0=C0, hom=hom[:8], het=het[:8], name=f"{prob.name}-ns{ns}")
+
+
+def outlet_pool(outlet=True, seed=3, nx=32, ny=24):
+    """nx x ny (32 x 24 by default), periodic in x, wall below; liquid (config-0 fluid) everywhere
+    but a vapour bubble of radius 5, a sideways and downward body force, two
+    species with A -> B."""
+    a, b, R = W.EOS_PAPER
+    T = 0.75 * W.critical_temperature(a, b, R)
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    bub = (xx - nx // 2) ** 2 + (yy - ny // 2) ** 2 <= 25
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rho1 = np.where(bub, W.RHO_V_075_PAPER, W.RHO_L_075_PAPER) + rng.uniform(-1e-4, 1e-4, (ny, nx))
+    C0 = np.zeros((2, ny, nx))
+    C0[0] = 1.0 + 0.1 * np.sin(2 * np.pi * xx / nx)
+    return W.uniform_problem(
+        nx, ny, periodic_x=True, periodic_y=False, outlet_top=outlet, ideal=False, a=a, b=b, R=R, T=T,
+        G11=-1.0, G12=0.5, G21=0.5, rho10=W.paper_rho10(), rho20=0.003, a0=0.005, rho1=1.0,
+        gbody=(2e-5, -1e-5), species=[W.Species("A", 1.0, 0.9), W.Species("B", 1.0, 0.9)],
+        hom=[W.HomRxn("first_order", re=(0, -1), pr=(1, -1), k=1e-3)],
+    ).copy(rho1=rho1, rho2=np.full((ny, nx), 0.1), C0=C0)

@@ -16,6 +16,7 @@ from scipy.optimize import brentq, fsolve
 from scipy.special import erf
 
 from oracle import OracleSim
+from parity import outlet_pool
 from paper_1410_3464_amd import workloads as W
 
 
@@ -523,27 +524,6 @@ def test_mass_conserved_without_reactions():
 # Free outlet (Sec. 5.1: the top of the beaker has zero gradient of every
 # variable)
 # --------------------------------------------------------------------------
-def _outlet_pool(outlet=True, seed=3):
-    """32 x 24, periodic in x, wall below; liquid (config-0 fluid) everywhere
-    but a vapour bubble of radius 5, a sideways and downward body force, two
-    species with A -> B."""
-    a, b, R = W.EOS_PAPER
-    T = 0.75 * W.critical_temperature(a, b, R)
-    nx, ny = 32, 24
-    yy, xx = np.mgrid[0:ny, 0:nx]
-    bub = (xx - 16) ** 2 + (yy - 12) ** 2 <= 25
-    rng = np.random.Generator(np.random.PCG64(seed))
-    rho1 = np.where(bub, W.RHO_V_075_PAPER, W.RHO_L_075_PAPER) + rng.uniform(-1e-4, 1e-4, (ny, nx))
-    C0 = np.zeros((2, ny, nx))
-    C0[0] = 1.0 + 0.1 * np.sin(2 * np.pi * xx / nx)
-    return W.uniform_problem(
-        nx, ny, periodic_x=True, periodic_y=False, outlet_top=outlet, ideal=False, a=a, b=b, R=R, T=T,
-        G11=-1.0, G12=0.5, G21=0.5, rho10=W.paper_rho10(), rho20=0.003, a0=0.005, rho1=1.0,
-        gbody=(2e-5, -1e-5), species=[W.Species("A", 1.0, 0.9), W.Species("B", 1.0, 0.9)],
-        hom=[W.HomRxn("first_order", re=(0, -1), pr=(1, -1), k=1e-3)],
-    ).copy(rho1=rho1, rho2=np.full((ny, nx), 0.1), C0=C0)
-
-
 def _arrivals_equal(sim):
     """Populations that arrive from above at the top row equal those that
     arrive at the row below it: D2Q9 directions 4, 7, 8 (e_y = -1) of both
@@ -560,14 +540,14 @@ def test_outlet_arrivals_have_zero_gradient():
     below it from the top row, step after step, while the body force and the
     bubble keep the top rows out of equilibrium.  The same lattice with a wall
     on top (bounce-back) fails the check, so it is not vacuous."""
-    s = OracleSim(_outlet_pool())
+    s = OracleSim(outlet_pool())
     for _ in range(6):
         s.step(5)
         F = s.fields()
         assert F["type"][-2:].min() == W.FLUID and F["liquid"][-2:].all()
         assert _arrivals_equal(s)
     s.close()
-    w = OracleSim(_outlet_pool(outlet=False))
+    w = OracleSim(outlet_pool(outlet=False))
     w.step(5)
     assert not _arrivals_equal(w)
     w.close()
