@@ -106,6 +106,19 @@ class LbrxError(RuntimeError):
 _lib = None
 
 
+def _init_torch_first():
+    """PyTorch carries its own HIP runtime.  When the library's runtime
+    initialises the device first, PyTorch's later finds no device, so PyTorch
+    (whose streams and allocator the binding uses) is initialised before the
+    library is loaded; without a device nothing is done."""
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.device_count() > 0:
+        torch.cuda.init()
+
+
 def load_library(path=LIB_PATH):
     """Load liblbrx.so; raises if it has not been built (no fallback exists)."""
     global _lib
@@ -113,6 +126,7 @@ def load_library(path=LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} not found: build it with `python -m paper_1410_3464_amd.build`")
+    _init_torch_first()
     lib = C.CDLL(path)
     lib.lbrx_create.restype = C.c_int
     lib.lbrx_create.argtypes = [C.POINTER(Params), C.c_void_p, C.POINTER(C.c_void_p)]

@@ -23,6 +23,45 @@ import numpy as np
 
 FLUID, SOLID_INERT, SOLID_D, SOLID_F = 0, 1, 2, 3
 
+def beaker(nx=100, ny=160, level=100, radius=15.0, centre=(50.0, 50.0), G12=0.5, seed=0,
+           species=("A",), hom=(), het=()):
+    """The beaker of Sec. 5 (100 x 160 lattice units of 1 mm): walls on the
+    left, right and bottom with w = 0 (90-degree contact angle), a free outlet
+    on top, a dissolvable D(s) particle of radius 15 at (50, 50) with volume 1.
+    Sec. 5.1's start: rho1 = 8.31, rho2 = 1e-4 below y = level, rho1 = 0.05,
+    rho2 = 0.05 above (joined by a tanh of width 1.5), at T = 0.65 T_c of the
+    adopted EOS set; tau = 1; every
+    species with J0 = 0.9, tau_g = 0.65 and, for the first one (A), C = 1 in
+    the liquid.  The paper's G12, G21 are in its Table 1, which is not
+    available; the default is that of the other workloads here.  Noise of
+    +-1e-6 (seeded) breaks the mirror symmetry.  Input description only."""
+    a, b, R = EOS_PAPER
+    T = 0.65 * critical_temperature(a, b, R)
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    t = np.zeros((ny, nx), np.uint8)
+    part = (xx - centre[0]) ** 2 + (yy - centre[1]) ** 2 <= radius ** 2
+    t[part] = SOLID_D
+    below = yy < level
+    # the step between the two phases as a tanh of width 1.5 (a sharp step
+    # drives the density negative at the interface within two steps)
+    s = 0.5 * (1.0 - np.tanh((yy + 0.5 - level) / 1.5))
+    rng = _rng(seed)
+    fl = t == FLUID
+    rho1 = np.where(fl, 0.05 + (8.31 - 0.05) * s + rng.uniform(-1e-6, 1e-6, (ny, nx)), 0.0)
+    rho2 = np.where(fl, 0.05 + (1e-4 - 0.05) * s, 0.0)
+    ns = len(species)
+    C0 = np.zeros((ns, ny, nx))
+    if ns:
+        C0[0] = np.where(fl & below, 1.0, 0.0)
+    return Problem(
+        name=f"beaker-{nx}x{ny}", nx=nx, ny=ny, periodic_x=False, periodic_y=False, outlet_top=True,
+        tau=(1.0, 1.0), a=a, b=b, R=R, T=T, G11=-1.0, G12=G12, G21=G12,
+        a0=0.005, rho10=paper_rho10(0.005), rho20=0.003,
+        species=[Species(n, tau_g=0.65, J0=0.9) for n in species], hom=list(hom), het=list(het),
+        type0=t, V0=np.where(part, 1.0, 0.0), rho1=rho1, rho2=rho2, C0=C0, steps=50000,
+    )
+
+
 # Carnahan-Starling parameter sets named in the text after Eq. 13: the original
 # (a=1, b=4, R=1) and the one the paper adopts because the two-component system
 # diverges at the small vapour density of the first (a=0.09926, b=0.18727, R=0.2).

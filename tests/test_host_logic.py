@@ -130,3 +130,23 @@ def test_algorithmic_bytes_on_a_hand_counted_case():
     assert b == 11 * 36 * 4 + 4 * 10 * 2 * 4 + 2 * 12 + 16 * 5
     b16, _ = bench.algorithmic_bytes({"type": t, "liquid": liq}, p, 2)
     assert b16 == 11 * 36 * 2 + 4 * 10 * 2 * 2 + 2 * 12 + 16 * 5 + 4 * 8
+
+
+def test_beaker_geometry():
+    """Sec. 5: 100 x 160 lattice units, walls left, right and below, a free
+    outlet on top, a D(s) particle of radius 15 at (50, 50) with volume 1,
+    liquid (8.31, 1e-4) below y = 100 and gas (0.05, 0.05) above, joined by
+    a tanh of width 1.5; A = 1 in the liquid only; T = 0.65 T_c."""
+    p = W.beaker()
+    assert (p.nx, p.ny) == (100, 160)
+    assert not p.periodic_x and not p.periodic_y and p.outlet_top
+    yy, xx = np.mgrid[0:160, 0:100]
+    part = (xx - 50) ** 2 + (yy - 50) ** 2 <= 225
+    assert np.array_equal(p.type0 == W.SOLID_D, part) and np.all(p.V0[part] == 1.0)
+    fl = ~part
+    assert np.all(np.abs(p.rho1[10][fl[10]] - 8.31) < 1e-5) and np.all(np.abs(p.rho1[150] - 0.05) < 1e-5)
+    assert np.allclose(p.rho2[10][fl[10]], 1e-4) and np.allclose(p.rho2[150], 0.05)
+    assert np.all(p.rho1[~fl] == 0.0)
+    assert np.all(p.C0[0][10][fl[10]] == 1.0) and np.all(p.C0[0][150] == 0.0)
+    assert p.species[0].tau_g == 0.65 and p.species[0].J0 == 0.9
+    assert math.isclose(p.T, 0.65 * W.critical_temperature(p.a, p.b, p.R))
