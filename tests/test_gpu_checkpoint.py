@@ -21,6 +21,41 @@ def _events():
     return events_problem()
 
 
+def _outlet_events():
+    import os
+    import sys
+
+    sys.path.insert(0, os.path.dirname(__file__))
+    from test_gpu_outlet import outlet_events
+
+    return outlet_events()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_resume_at_the_outlet(precision):
+    """The event-heavy case at the free outlet: the state blob carries the
+    top row's slot-2 copies that the ghost row sends, so 137 steps, save,
+    load, 63 steps equals 200 steps straight bit for bit."""
+    from paper_1410_3464_amd.lbrx import Lbrx
+
+    prob = _outlet_events()
+    ref = Lbrx(prob, precision)
+    ref.step(200)
+    R = ref.fields()
+    ref.close()
+    a = Lbrx(prob, precision)
+    a.step(137)
+    blob = a.save_state()
+    a.close()
+    b = Lbrx(prob, precision)
+    b.load_state(blob)
+    b.step(63)
+    G = b.fields()
+    b.close()
+    for k in KEYS:
+        assert np.array_equal(G[k], R[k]), k
+
+
 @pytest.mark.parametrize("precision", ["f64", "f32", "f16dev"])
 def test_resume_equals_uninterrupted(precision):
     """The event-heavy case (dissolution, precipitation and moving interfaces
