@@ -69,3 +69,22 @@ def test_unstable_request_fails_alone():
             continue
         for k in KEYS:
             assert np.array_equal(r.fields[k], alone[r.rid].fields[k]), (r.rid, k)
+
+
+def test_outlet_request_in_the_mix():
+    """A porous request whose top side is the free outlet joins FP32 requests
+    of the same species count: its batch then runs the outlet kernels for all
+    members, and every request still ends with the fields of its run alone."""
+    from paper_1410_3464_amd import serve
+    from paper_1410_3464_amd import workloads as W
+
+    reqs = serve.poisson_requests(5, 0.002, seed=11, steps=(40, 90), sizes=(64, 128), precisions=("f32",))
+    out = W.batch_instance(12, smin=64, smax=96).copy(outlet_top=True)
+    reqs.insert(1, serve.Request(98, out, 70, "f32", reqs[0].arrival))
+    mixed = serve.Server(tick=20, keep_fields=True).run(reqs)
+    alone_reqs = serve.clone_requests(reqs)
+    plain = serve.run_plain(alone_reqs, keep_fields=True)
+    assert mixed["completed"] == plain["completed"] == len(reqs)
+    for a, b in zip(reqs, alone_reqs):
+        for k in KEYS:
+            assert np.array_equal(a.fields[k], b.fields[k]), (a.rid, k)
