@@ -10,7 +10,8 @@ Permeability of a dissolving fracture against porosity (App. A.3, Eq. A2,
 A3, Fig. A3) on the paper's 100 x 90 box.
 
 The two-phase beaker of Sec. 5.1 (Fig. 3) with its free outlet, against
-the printed liquid density and density ratio after 50,000 steps.
+the printed liquid density and density ratio after 50,000 steps; the
+decomposition of A in it (Sec. 5.2.1, Fig. 4a-b).
 """
 import json
 import math
@@ -239,3 +240,38 @@ def test_beaker_two_phase_system():
     assert abs((liq / gas) / gold["density_ratio"] - 1) < 0.10
     assert band < 0.01
     assert np.ptp(levels) < 1.5 and all(abs(v - gold["initial_level_y"]) < 3 for v in levels)
+
+
+def test_beaker_decomposition_of_A():
+    """Sec. 5.2.1 (Fig. 4a-b) in the beaker: only R1 (A -> B + C(g)) runs,
+    1000 times faster at the D(s) surface than in the bulk (Sec. 2), from the
+    Sec. 5.1 start, FP64, 20,000 steps.  As the paper describes, A is
+    decomposed faster next to the particle (mean C_A in the liquid within 2.5
+    nodes of its surface below 90 % of the mean far from it) and B is higher
+    there; and the liquid-gas interface passes no A or B: the totals of A + B
+    stay at their start less what the status-change amendments booked as
+    removed, to 1e-10 relative (R1 turns A into B one for one)."""
+    from paper_1410_3464_amd.lbrx import Lbrx
+
+    r1 = W.HomRxn("r1_gas", re=(0, -1), pr=(1, -1), k=1e-6, K_eq=1.0, M_gas=1e-3,
+                  surface=(W.SOLID_D,), surface_factor=1000.0)
+    p = W.beaker(species=("A", "B"), hom=(r1,))
+    g = Lbrx(p, "f64")
+    F0 = g.fields()
+    total0 = F0["C"].sum()
+    g.step(20000)
+    F = g.fields()
+    g.close()
+    yy, xx = np.mgrid[0:p.ny, 0:p.nx]
+    d = np.hypot(xx - 50, yy - 50)
+    lq = F["liquid"].astype(bool)
+    near = lq & (d > 15) & (d <= 17.5)
+    far = lq & (d > 30) & (yy > 10) & (yy < 90)
+    CA, CB = F["C"][0], F["C"][1]
+    L = F["ledger"]
+    removed = float(np.sum(np.asarray(L["sol_rem"])[:2]))
+    print(f"[beaker R1] C_A near {CA[near].mean():.4f} far {CA[far].mean():.4f}; C_B near {CB[near].mean():.4f} "
+          f"far {CB[far].mean():.4f}; A+B {F['C'].sum():.6f} start {total0:.6f} removed {removed:.3e}", flush=True)
+    assert CA[near].mean() < 0.9 * CA[far].mean()
+    assert CB[near].mean() > CB[far].mean()
+    assert abs(F["C"].sum() - (total0 - removed)) < 1e-10 * total0
