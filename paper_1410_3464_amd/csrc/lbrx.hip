@@ -2155,8 +2155,10 @@ lbrx_status lbrx_step(lbrx_ctx* x, int64_t n) {
           x->steps += 1;
         }
         x->steps = s0;
+        const hipError_t le = hipGetLastError();  // a launch refused while capturing
         const hipError_t e = hipStreamEndCapture(x->stream, &x->graph);
-        if (e != hipSuccess || hipGraphInstantiate(&x->gexec, x->graph, nullptr, nullptr, 0) != hipSuccess) {
+        if (le != hipSuccess || e != hipSuccess ||
+            hipGraphInstantiate(&x->gexec, x->graph, nullptr, nullptr, 0) != hipSuccess) {
           if (x->graph) (void)hipGraphDestroy(x->graph);
           x->graph = nullptr;
           x->gexec = nullptr;
