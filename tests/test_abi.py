@@ -74,3 +74,28 @@ def test_missing_library_fails_loudly(tmp_path):
             lbrx.load_library(str(tmp_path / "nope.so"))
     finally:
         lbrx._lib = saved
+
+
+def test_create_validates_before_touching_the_device():
+    """lbrx_create checks the problem before any device call, so its refusals
+    show without a GPU: a free outlet with 16-bit storage or with a periodic
+    y axis, unknown boundary bits, tau <= 1/2; each with a message."""
+    from paper_1410_3464_amd import lbrx
+    from paper_1410_3464_amd import workloads as W
+
+    if not os.path.exists(lbrx.LIB_PATH):
+        pytest.skip("liblbrx.so not built (run __graft_entry__.build())")
+    lib = lbrx.load_library()
+    p = W.beaker(nx=20, ny=24, level=12, radius=3.0, centre=(10.0, 8.0))
+    cases = [(p, "f16dev", "FP64 or FP32"), (p, "bf16dev", "FP64 or FP32"),
+             (p.copy(periodic_y=True), "f64", "walls in y"), (p.copy(tau=(0.5, 1.0)), "f32", "tau")]
+    for prob, prec, words in cases:
+        with pytest.raises(lbrx.LbrxError) as ei:
+            lbrx.Lbrx(prob, prec)
+        assert ei.value.status == 1 and words in str(ei.value), (prec, str(ei.value))
+    params, keep = lbrx.make_params(p, "f64", 0)
+    params.periodic = 8
+    h = ctypes.c_void_p()
+    assert lib.lbrx_create(ctypes.byref(params), None, ctypes.byref(h)) == 1
+    assert b"unknown bits" in lib.lbrx_create_error()
+    del keep
