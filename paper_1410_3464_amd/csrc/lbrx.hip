@@ -1497,7 +1497,8 @@ __global__ __launch_bounds__(LSUM_THREADS) void k_ledger_sum(const double* led, 
 }
 
 // ---------------------------------------------------------------- host side
-constexpr int SEG_ROWS = 12;  // default rows per item (LBRX_SEG_ROWS overrides, 1..HMAX)
+constexpr int SEG_ROWS = 12;      // default rows per item (LBRX_SEG_ROWS overrides, 1..HMAX)
+constexpr int SEG_ROWS_F64 = 16;  // FP64 storage (one wavefront per SIMD): taller items
 // Steps per captured HIP graph of launches: a multiple of 6, the period of
 // the step phases (buffer parity and rho_max slot), so that one graph serves
 // every replay that starts at a step count divisible by 6.
@@ -1964,7 +1965,7 @@ lbrx_status lbrx_create(const lbrx_params* p, void* hip_stream, lbrx_ctx** out) 
   x->precision = p->precision;
   x->esz = storage_bytes(p->precision);
   c.sg = species_group(c.ns, (int)x->esz);
-  c.seg_rows = p->seg_rows > 0 ? p->seg_rows : SEG_ROWS;
+  c.seg_rows = p->seg_rows > 0 ? p->seg_rows : (p->precision == LBRX_F64 ? SEG_ROWS_F64 : SEG_ROWS);
   if (const char* e = getenv("LBRX_SEG_ROWS")) {
     const int v = atoi(e);
     if (v >= 1 && v <= HMAX) c.seg_rows = v;
