@@ -12,7 +12,7 @@ A3, Fig. A3) on the paper's 100 x 90 box.
 The two-phase beaker of Sec. 5.1 (Fig. 3) with its free outlet, against
 the printed liquid density and density ratio after 50,000 steps; the
 decomposition of A in it and the escape of the released gas (Sec. 5.2.1,
-Fig. 4a-c).
+Fig. 4a-c); the dissolution of its particle (Sec. 5.2.2, Fig. 5).
 """
 import json
 import math
@@ -305,3 +305,44 @@ def test_beaker_gas_lower_above_the_particle():
     below = F["rho2"][near & (yy < 45)].mean()
     print(f"[beaker R1 gas] above {above:.4e} below {below:.4e} ratio {above / below:.3f}", flush=True)
     assert above < 0.95 * below
+
+
+def test_beaker_particle_dissolves():
+    """Sec. 5.2.2 (Fig. 5): R1 as above plus the dissolution R2 at the D(s)
+    surface (B consumed, E released, Eq. 29-33), FP64.  As the paper
+    describes, the particle shrinks (fewer than half of its 709 nodes left
+    after 20,000 steps) and E, released at its surface, gathers around it
+    (mean C_E within 2.5 nodes of the remaining particle over 5 times the
+    mean far away, and higher at 20,000 steps than at 2,000).  The surface
+    exchange is exact: what R2 took of B equals what it gave to E (balance
+    records, 1e-12 relative)."""
+    from paper_1410_3464_amd.lbrx import Lbrx
+
+    r1 = W.HomRxn("r1_gas", re=(0, -1), pr=(1, -1), k=1e-6, K_eq=1.0, M_gas=1e-3,
+                  surface=(W.SOLID_D,), surface_factor=1000.0)
+    r2 = W.HetRxn(reactant=1, product=2, surface=(W.SOLID_D,), mode="consumes", irreversible=True,
+                  k=1e-2, C_eq=0.0, molar_volume=1.0)
+    p = W.beaker(species=("A", "B", "E"), hom=(r1,), het=(r2,))
+    n0 = int((p.type0 == W.SOLID_D).sum())
+    yy, xx = np.mgrid[0:p.ny, 0:p.nx]
+    d = np.hypot(xx - 50, yy - 50)
+    g = Lbrx(p, "f64")
+    e_near = []
+    for n in (2000, 20000):
+        g.step(n - (2000 if n > 2000 else 0))
+        F = g.fields()
+        nD = int((F["type"] == W.SOLID_D).sum())
+        rD = np.sqrt(nD / np.pi)
+        lq = F["liquid"].astype(bool)
+        near = lq & (d > rD) & (d <= rD + 2.5)
+        far = lq & (d > 30) & (yy > 10) & (yy < 90)
+        CE = F["C"][2]
+        e_near.append(CE[near].mean())
+        print(f"[beaker R2] step {n}: D nodes {nD}/{n0}, C_E near {CE[near].mean():.4f} far {CE[far].mean():.4f}",
+              flush=True)
+        assert CE[near].mean() > 5 * CE[far].mean()
+    g.close()
+    assert nD < 0.5 * n0
+    assert e_near[1] > e_near[0]
+    het = np.asarray(F["ledger"]["sol_het"])
+    assert het[1] < 0 and abs(het[1] + het[2]) < 1e-12 * abs(het[1])
