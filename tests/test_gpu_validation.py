@@ -12,7 +12,8 @@ A3, Fig. A3) on the paper's 100 x 90 box.
 The two-phase beaker of Sec. 5.1 (Fig. 3) with its free outlet, against
 the printed liquid density and density ratio after 50,000 steps; the
 decomposition of A in it and the escape of the released gas (Sec. 5.2.1,
-Fig. 4a-c); the dissolution of its particle (Sec. 5.2.2, Fig. 5).
+Fig. 4a-c); the dissolution of its particle (Sec. 5.2.2, Fig. 5) and its
+coating by precipitate (Sec. 5.2.3, Fig. 6).
 """
 import json
 import math
@@ -346,3 +347,44 @@ def test_beaker_particle_dissolves():
     assert e_near[1] > e_near[0]
     het = np.asarray(F["ledger"]["sol_het"])
     assert het[1] < 0 and abs(het[1] + het[2]) < 1e-12 * abs(het[1])
+
+
+def test_beaker_precipitate_coats_the_particle_and_lifts_the_level():
+    """Sec. 5.2.3 (Fig. 6): all four reactions (R1, R2, R3: B + E -> F,
+    R4: F -> F(s) on D(s) and F(s)), FP64, 30,000 steps.  As the paper
+    describes, F(s) grows on the particle's surface (over 100 precipitated
+    nodes, their mean distance from its centre between 15 and 19, the
+    particle's radius being 15), the coating halts the dissolution (at
+    least 95 % of D(s) left), and the liquid-gas interface rises because the
+    precipitate takes the liquid's place: above y = 103 across the beaker
+    (measured 104.7; the beaker without reactions settles at 100.9-101.7)."""
+    from paper_1410_3464_amd.lbrx import Lbrx
+
+    hom = (W.HomRxn("r1_gas", re=(0, -1), pr=(1, -1), k=1e-6, K_eq=1.0, M_gas=1e-3,
+                    surface=(W.SOLID_D,), surface_factor=1000.0),
+           W.HomRxn("bimolecular", re=(1, 2), pr=(3, -1), k=1e-2))
+    het = (W.HetRxn(reactant=1, product=2, surface=(W.SOLID_D,), mode="consumes", irreversible=True,
+                    k=1e-2, C_eq=0.0, molar_volume=1.0),
+           W.HetRxn(reactant=3, product=-1, surface=(W.SOLID_D, W.SOLID_F), mode="grows",
+                    irreversible=True, k=1e-1, C_eq=0.0, molar_volume=10.0))
+    p = W.beaker(species=("A", "B", "E", "F"), hom=hom, het=het)
+    n0 = int((p.type0 == W.SOLID_D).sum())
+    g = Lbrx(p, "f64")
+    g.step(30000)
+    F = g.fields()
+    g.close()
+    t = F["type"]
+    fs = np.argwhere(t == W.SOLID_F)
+    dist = np.hypot(fs[:, 1] - 50, fs[:, 0] - 50).mean()
+    r1 = F["rho1"]
+    levels = []
+    for c in (5, 20, 80, 94):
+        col = r1[:, c]
+        mid = 4.1
+        k = next(y for y in range(70, p.ny - 1) if (col[y] - mid) * (col[y + 1] - mid) < 0)
+        levels.append(k + (col[k] - mid) / (col[k] - col[k + 1]))
+    print(f"[beaker all] F(s) {len(fs)} at mean distance {dist:.1f}; D(s) {int((t == W.SOLID_D).sum())}/{n0}; "
+          "levels " + " ".join(f"{v:.2f}" for v in levels), flush=True)
+    assert len(fs) > 100 and 15 < dist < 19
+    assert (t == W.SOLID_D).sum() >= 0.95 * n0
+    assert min(levels) > 103
