@@ -13,7 +13,8 @@ The two-phase beaker of Sec. 5.1 (Fig. 3) with its free outlet, against
 the printed liquid density and density ratio after 50,000 steps; the
 decomposition of A in it and the escape of the released gas (Sec. 5.2.1,
 Fig. 4a-c); the dissolution of its particle (Sec. 5.2.2, Fig. 5) and its
-coating by precipitate (Sec. 5.2.3, Fig. 6).
+coating by precipitate (Sec. 5.2.3, Fig. 6); the order of the solid
+volumes across reaction sets and precipitation rates (Sec. 5.3-5.4).
 """
 import json
 import math
@@ -388,3 +389,43 @@ def test_beaker_precipitate_coats_the_particle_and_lifts_the_level():
     assert len(fs) > 100 and 15 < dist < 19
     assert (t == W.SOLID_D).sum() >= 0.95 * n0
     assert min(levels) > 103
+
+
+def test_beaker_solid_volumes_order():
+    """Sec. 5.3-5.4 (Fig. 8, 10): total solid volumes after 30,000 FP64
+    steps of the beaker.  The particle dissolves quickest with R1 and R2 alone
+    (no precipitate competes for B or covers the surface), more slowly with
+    all four reactions, and the slower the precipitation R4 the more of it
+    dissolves: V_D(R1+R2) < V_D(k4 / 10^4) < V_D(k4), and V_D(k4 / 2 10^4)
+    not above V_D(k4 / 10^4); the precipitate volume (SOLID_F nodes plus the
+    precipitate still held by liquid nodes) grows with k4."""
+    from paper_1410_3464_amd.lbrx import Lbrx
+
+    r1 = W.HomRxn("r1_gas", re=(0, -1), pr=(1, -1), k=1e-6, K_eq=1.0, M_gas=1e-3,
+                  surface=(W.SOLID_D,), surface_factor=1000.0)
+    r3 = W.HomRxn("bimolecular", re=(1, 2), pr=(3, -1), k=1e-2)
+    r2 = W.HetRxn(reactant=1, product=2, surface=(W.SOLID_D,), mode="consumes", irreversible=True,
+                  k=1e-2, C_eq=0.0, molar_volume=1.0)
+
+    def r4(k):
+        return W.HetRxn(reactant=3, product=-1, surface=(W.SOLID_D, W.SOLID_F), mode="grows",
+                        irreversible=True, k=k, C_eq=0.0, molar_volume=10.0)
+
+    sp = ("A", "B", "E", "F")
+    cases = {"R1+R2": W.beaker(species=sp, hom=(r1,), het=(r2,)),
+             "k4": W.beaker(species=sp, hom=(r1, r3), het=(r2, r4(1e-1))),
+             "k4/1e4": W.beaker(species=sp, hom=(r1, r3), het=(r2, r4(1e-5))),
+             "k4/2e4": W.beaker(species=sp, hom=(r1, r3), het=(r2, r4(5e-6)))}
+    VD, VF = {}, {}
+    for name, p in cases.items():
+        g = Lbrx(p, "f64")
+        g.step(30000)
+        F = g.fields()
+        g.close()
+        t, V = F["type"], F["V"]
+        VD[name] = V[t == W.SOLID_D].sum()
+        VF[name] = V[t == W.SOLID_F].sum() + V[t == W.FLUID].sum()
+        print(f"[beaker volumes] {name}: V_D {VD[name]:.1f} V_F {VF[name]:.1f}", flush=True)
+    assert VD["R1+R2"] < VD["k4/1e4"] < VD["k4"]
+    assert VD["k4/2e4"] <= VD["k4/1e4"] + 1e-9
+    assert VF["k4"] > VF["k4/1e4"] > VF["k4/2e4"] > 0
