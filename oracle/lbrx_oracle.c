@@ -5,30 +5,41 @@
  *
  * One step, in the order of Sec. 4.7 (Steps 1-5); every sub-step is one
  * full-lattice pass over plain arrays:
- *   1  moments of the streamed populations (Eq. 9, 23)
+ *   1  moments of the streamed populations (Eq. 9, 23): the flow field of
+ *      Step 1 is the result of the previous collision and streaming
  *   2  effective masses psi_1 (Eq. 12-13), phi_1, phi_2 (Eq. 15)
- *   3  maximum liquid-component density (Sec. 4.5 threshold, used next step)
+ *   3  liquid marks from this step's densities (Sec. 4.5; Step 2), and the
+ *      maximum liquid-component density that sets the next step's threshold
  *   4  forces: cohesion (Eq. 11), inter-component (Eq. 14), adhesion (Eq. 16), body force
  *   5  velocities (Eq. 17-19)
  *   6  homogeneous reaction sources at liquid nodes (Eq. 5, 27, 28)
- *   7  flow collision (Eq. 6, 8) and solute collision (Eq. 20-22)
+ *   7  flow collision (Eq. 6, 8) and solute collision (Eq. 20-22) (Step 3)
  *   8  heterogeneous link fluxes (Eq. 29-31, A2) in halfway-wall Robin form
- *   9  volume-of-pixel update (Eq. 33, 35) and the new node types
- *  10  amendments for nodes that changed status (Sec. 4.5)
- *  11  liquid marks for the next step (Sec. 4.5)
- *  12  push streaming with halfway bounce-back and reactive flux
+ *   9  volume-of-pixel update (Eq. 33, 35) and the new node types (Step 4)
+ *  10  amendments for nodes that changed status (Sec. 4.5; Steps 2 and 5)
+ *  11  push streaming with halfway bounce-back and reactive flux
  * Readings of the places where the paper is silent are stated where used.
  * Parity unpinned (no closed form, invariant or printed value fixes them
  * beyond conservation, which the tests check): which density each phi of
- * Eq. 15 takes, the one-step lag of the liquid threshold's maximum
- * density, the details of the status-change amendments of Sec. 4.5, and
- * the time level of the velocity in the solute equilibrium.
+ * Eq. 15 takes, the threshold's maximum density taken one step back, the
+ * details of the status-change amendments of Sec. 4.5, and the time level
+ * of the velocity in the solute equilibrium.
  */
 #include "lbrx_oracle.h"
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Solute a node holds at the start of a step (Sec. 4.5 amendments):
+ *   SF_STREAM  it was liquid in the previous step; its slots hold the
+ *              populations streamed into it
+ *   SF_HOLD    it is not liquid and keeps its content at rest in its own
+ *              slots (no liquid D2Q5 neighbour could take it)
+ *   SF_SHARE   it left the liquid set last step; its slots hold, at rest,
+ *              the share of its content due to each D2Q5 neighbour that was
+ *              liquid then, delivered during this step */
+enum { SF_NONE = 0, SF_STREAM = 1, SF_HOLD = 2, SF_SHARE = 3 };
 
 /* D2Q9 velocities (Eq. 7); D2Q5 uses directions 0..4 of the same table (Sec. 3.2). */
 static const int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
@@ -50,14 +61,16 @@ struct orc_sim {
   double *fs, *gs;          /* post-collision scratch */
   double *fn, *gn;          /* next-step buffers */
   uint8_t *type;            /* T(n) */
-  uint8_t *liq, *liqprev;   /* L(n), L(n-1) */
+  uint8_t *liq;             /* liquid mark of this step, L(n) */
+  uint8_t *sflag;           /* solute held at the start of the step (SF_*) */
   uint8_t *stranded;        /* node became SOLID_F at the end of the previous step */
   double *V;
   double rho_max_prev;
   orc_ledger led;
   /* per-step work arrays */
   double *rho, *jx, *jy;    /* [2][N] */
-  double *C;                /* [ns][N] */
+  double *C;                /* [ns][N] moments of the solute slots */
+  double *Cin;              /* [ns][N] shares received from nodes that left the liquid */
   double *psi1, *phi1, *phi2;
   double *Fx, *Fy;          /* [2][N] */
   double *ueqx, *ueqy;      /* [2][N] */
@@ -66,6 +79,7 @@ struct orc_sim {
   double *Sk;               /* solute sources [ns][N] */
   double *Phi;              /* link flux per het reaction [n_het][N] */
   uint8_t *tnext;           /* T(n+1) */
+  uint8_t *snext;           /* solute held at the start of the next step */
   double *rbar;             /* [2][N] mean density put into dissolved nodes */
   double D[ORC_MAX_SPECIES];
   double kap[ORC_MAX_RXN];
@@ -185,14 +199,16 @@ orc_sim* orc_create(const orc_params* p, const uint8_t* type0, const double* V0,
   s->gn = xcalloc((size_t)5 * ns * N + 1, sizeof(double));
   s->type = xcalloc(N, 1);
   s->liq = xcalloc(N, 1);
-  s->liqprev = xcalloc(N, 1);
+  s->sflag = xcalloc(N, 1);
   s->stranded = xcalloc(N, 1);
   s->tnext = xcalloc(N, 1);
+  s->snext = xcalloc(N, 1);
   s->V = xcalloc(N, sizeof(double));
   s->rho = xcalloc((size_t)2 * N, sizeof(double));
   s->jx = xcalloc((size_t)2 * N, sizeof(double));
   s->jy = xcalloc((size_t)2 * N, sizeof(double));
   s->C = xcalloc((size_t)ns * N + 1, sizeof(double));
+  s->Cin = xcalloc((size_t)ns * N + 1, sizeof(double));
   s->psi1 = xcalloc(N, sizeof(double));
   s->phi1 = xcalloc(N, sizeof(double));
   s->phi2 = xcalloc(N, sizeof(double));
@@ -237,7 +253,7 @@ orc_sim* orc_create(const orc_params* p, const uint8_t* type0, const double* V0,
     }
     if (rho1[i] > thr) {
       s->liq[i] = 1;
-      s->liqprev[i] = 1;
+      s->sflag[i] = SF_STREAM;
       for (int k = 0; k < ns; ++k) {
         const double J1 = 0.25 * (1.0 - p->J0[k]);
         for (int a = 0; a < 5; ++a)
@@ -250,7 +266,7 @@ orc_sim* orc_create(const orc_params* p, const uint8_t* type0, const double* V0,
 
 void orc_destroy(orc_sim* s) {
   if (!s) return;
-  void* ptrs[] = {s->f, s->fs, s->fn, s->g, s->gs, s->gn, s->type, s->liq, s->liqprev,
+  void* ptrs[] = {s->f, s->fs, s->fn, s->g, s->gs, s->gn, s->type, s->liq, s->sflag, s->Cin, s->snext,
                   s->stranded, s->tnext, s->V, s->rho, s->jx, s->jy, s->C, s->psi1,
                   s->phi1, s->phi2, s->Fx, s->Fy, s->ueqx, s->ueqy, s->urx, s->ury,
                   s->Ss, s->Sk, s->Phi, s->rbar};
@@ -284,9 +300,8 @@ static int macros(orc_sim* s) {
 
   /* 1. moments (Eq. 9, 23).  f is valid at fluid nodes and at nodes that
    * turned solid at the end of the previous step (their streamed-in
-   * populations are still there).  g is valid where the node was liquid in
-   * the previous step; a node that has just become liquid carries no solute
-   * yet (its distributions are set to zero). */
+   * populations are still there).  g is valid where the node holds solute
+   * (SF_*); at an SF_SHARE node its moment is the share in transit. */
   for (int i = 0; i < N; ++i) {
     const int validf = s->type[i] == ORC_FLUID || s->stranded[i];
     for (int sg = 0; sg < 2; ++sg) {
@@ -313,11 +328,8 @@ static int macros(orc_sim* s) {
     }
     for (int k = 0; k < ns; ++k) {
       double c = 0.0;
-      if (s->liqprev[i]) {
+      if (s->sflag[i] != SF_NONE)
         for (int a = 0; a < 5; ++a) c += s->g[(k * 5 + a) * N + i];
-      } else if (s->liq[i]) {
-        for (int a = 0; a < 5; ++a) s->g[(k * 5 + a) * N + i] = 0.0;
-      }
       s->C[k * N + i] = c;
     }
   }
@@ -446,17 +458,55 @@ static int macros(orc_sim* s) {
   return 0;
 }
 
+/*
+ * Step 2 of Sec. 4.7 (Sec. 4.5): the liquid marks of this step and the
+ * solute shares that nodes which left the liquid set last step deliver now.
+ * A fluid node is liquid when its liquid-component density exceeds
+ * liquid_frac times the largest such density of the previous step (the
+ * maximum of the current step is only known once every node is updated).
+ * Cin of a node that was liquid last step (SF_STREAM) is the sum of the
+ * shares of its SF_SHARE D2Q5 neighbours: they split their content equally
+ * among the neighbours that were liquid when they left.  A ghost node beyond
+ * a free outlet neither gives nor takes.
+ */
+static void mark_liquid(orc_sim* s) {
+  const orc_params* p = &s->p;
+  const int N = s->N, ns = s->ns, nx = p->nx;
+  const double thr = p->liquid_frac * s->rho_max_prev;
+  for (int i = 0; i < N; ++i) s->liq[i] = s->type[i] == ORC_FLUID && s->rho[i] > thr;
+  for (int i = 0; i < N; ++i) {
+    for (int k = 0; k < ns; ++k) s->Cin[k * N + i] = 0.0;
+    if (s->sflag[i] != SF_STREAM) continue;
+    for (int a = 1; a < 5; ++a) {
+      const int j = nb_node(s, i % nx, i / nx, a);
+      if (j < 0 || s->sflag[j] != SF_SHARE) continue;
+      for (int k = 0; k < ns; ++k) s->Cin[k * N + i] += s->C[k * N + j];
+    }
+  }
+}
+
 int orc_step(orc_sim* s, int nsteps) {
   const orc_params* p = &s->p;
   const int N = s->N, ns = s->ns, nx = p->nx, ny = p->ny;
   for (int it = 0; it < nsteps; ++it) {
     if (macros(s) != 0) return -1;
 
-    /* 3. maximum rho_1 over fluid nodes at this step; it sets the liquid
-     * threshold of the decision taken one step later. */
+    /* 3. liquid marks of this step; maximum rho_1 over fluid nodes, which
+     * sets the threshold of the next step.  A node that has just become
+     * liquid holds the content it kept, if any; otherwise it starts with no
+     * solute (diffusion fills it). */
+    mark_liquid(s);
     double rmax_now = 0.0;
-    for (int i = 0; i < N; ++i)
+    for (int i = 0; i < N; ++i) {
       if (s->type[i] == ORC_FLUID && s->rho[i] > rmax_now) rmax_now = s->rho[i];
+      if (s->liq[i] && (s->sflag[i] == SF_NONE || s->sflag[i] == SF_SHARE))
+        for (int k = 0; k < ns; ++k) {
+          s->C[k * N + i] = 0.0;
+          for (int a = 0; a < 5; ++a) s->g[(k * 5 + a) * N + i] = 0.0;
+        }
+      if (s->sflag[i] == SF_STREAM && !s->liq[i] && s->type[i] == ORC_FLUID) s->led.n_liq_to_gas += 1.0;
+      if (s->liq[i] && s->sflag[i] != SF_STREAM) s->led.n_gas_to_liq += 1.0;
+    }
 
     /* 6. homogeneous reaction sources at liquid nodes (Eq. 5a, 5c, 27, 28;
      * a first-order A -> B law is also available).  C_C = rho_2 / M_gas. */
@@ -608,13 +658,17 @@ int orc_step(orc_sim* s, int nsteps) {
      * difference in the ledger:
      *  (a) stranded populations of a node that became SOLID_F last step are
      *      shared equally by its fluid D2Q9 neighbours, at rest;
-     *  (b) the solute of a node that left the liquid set (to gas or to solid)
-     *      is shared equally by its liquid D2Q5 neighbours, at rest;
+     *  (b) the solute of a node that is not liquid now (it left the liquid
+     *      set, to gas or to solid) goes in equal shares, at rest, to the
+     *      D2Q5 neighbours that are liquid now; they take the shares one step
+     *      later (so that every node involved is at most one link away); a
+     *      node with no such neighbour keeps its content until it has one;
      *  (c) a node freed by dissolution this step starts, next step, at rest
      *      with the mean density of its fluid D2Q9 neighbours (the added mass
-     *      is booked) and with no solute;
-     *  (d) a node that has just turned liquid starts with no solute (done in
-     *      the moments above); diffusion fills it. */
+     *      is booked);
+     *  (d) a node that has just turned liquid starts with the solute it kept,
+     *      if any, else with none (done with the marks above); diffusion
+     *      fills it. */
     for (int i = 0; i < N; ++i) {
       const int x = i % nx, y = i / nx;
       if (s->type[i] == ORC_FLUID) {
@@ -633,24 +687,10 @@ int orc_step(orc_sim* s, int nsteps) {
           if (don[sg] != 0.0)
             for (int a = 0; a < 9; ++a) s->fs[(sg * 9 + a) * N + i] += W9[a] * don[sg];
       }
-      if (s->liq[i]) {
-        double donk[ORC_MAX_SPECIES] = {0};
-        int any = 0;
-        for (int a = 1; a < 5; ++a) {
-          const int j = nb_node(s, x, y, a);
-          if (j < 0 || !(s->liqprev[j] && !s->liq[j])) continue;
-          int m = 0;
-          for (int b = 1; b < 5; ++b) {
-            const int q = nb_node(s, j % nx, j / nx, b);
-            if (q >= 0 && s->liq[q]) ++m;
-          }
-          for (int k = 0; k < ns; ++k) donk[k] += s->C[k * N + j] / m;
-          any = 1;
-        }
-        if (any)
-          for (int k = 0; k < ns; ++k)
-            for (int a = 0; a < 5; ++a) s->gs[(k * 5 + a) * N + i] += J_of(p, k, a) * donk[k];
-      }
+      if (s->liq[i] && s->sflag[i] == SF_STREAM)
+        for (int k = 0; k < ns; ++k)
+          if (s->Cin[k * N + i] != 0.0)
+            for (int a = 0; a < 5; ++a) s->gs[(k * 5 + a) * N + i] += J_of(p, k, a) * s->Cin[k * N + i];
     }
     /* donors with nobody to take their content */
     for (int i = 0; i < N; ++i) {
@@ -664,17 +704,29 @@ int orc_step(orc_sim* s, int nsteps) {
         if (m == 0)
           for (int sg = 0; sg < 2; ++sg) s->led.mass_rem[sg] += s->rho[sg * N + i];
       }
-      if (s->liqprev[i] && !s->liq[i]) {
+      /* (b) a node that holds solute but is not liquid now (it left the
+       * liquid set, or kept its content earlier) passes its content, plus
+       * the shares it received, to the D2Q5 neighbours that are liquid now:
+       * its slots carry, at rest, one equal share per such neighbour, which
+       * they take next step.  With no liquid neighbour it keeps the content
+       * at rest.  Nothing is dropped. */
+      s->snext[i] = s->liq[i] ? SF_STREAM : SF_NONE;
+      if (!s->liq[i] && (s->sflag[i] == SF_STREAM || s->sflag[i] == SF_HOLD) && ns > 0) {
         int m = 0;
         for (int b = 1; b < 5; ++b) {
           const int q = nb_node(s, x, y, b);
           if (q >= 0 && s->liq[q]) ++m;
         }
-        if (m == 0)
-          for (int k = 0; k < ns; ++k) s->led.sol_rem[k] += s->C[k * N + i];
-        if (s->type[i] == ORC_FLUID) s->led.n_liq_to_gas += 1.0;
+        int any = 0;
+        for (int k = 0; k < ns; ++k) {
+          double c = s->C[k * N + i];
+          if (s->sflag[i] == SF_STREAM) c += s->Cin[k * N + i];
+          if (m > 0) c = c / m;
+          if (c != 0.0) any = 1;
+          for (int a = 0; a < 5; ++a) s->gn[(k * 5 + a) * N + i] = J_of(p, k, a) * c;
+        }
+        if (any) s->snext[i] = m > 0 ? SF_SHARE : SF_HOLD;
       }
-      if (s->liq[i] && !s->liqprev[i]) s->led.n_gas_to_liq += 1.0;
     }
     /* (c) dissolved nodes: mean density of fluid neighbours */
     for (int i = 0; i < N; ++i) {
@@ -698,13 +750,7 @@ int orc_step(orc_sim* s, int nsteps) {
       s->led.vol_clip += s->V[i];
     }
 
-    /* 11. liquid marks for the next step (Sec. 4.5): a node that is fluid in
-     * the next step is liquid iff its density this step exceeds liquid_frac
-     * times the maximum of the previous step.  A freshly dissolved node is
-     * judged on the density it is given. */
-    const double thr = p->liquid_frac * s->rho_max_prev;
-
-    /* 12. push streaming (Eq. 6, 20, left-hand sides) with the masks of this
+    /* 11. push streaming (Eq. 6, 20, left-hand sides) with the masks of this
      * step.  Flow: halfway bounce-back off any non-fluid neighbour or
      * non-periodic boundary.  Solute: the liquid set only; bounce-back off gas
      * (the no-flux liquid-gas interface of Eq. 26) and solid, minus the
@@ -774,16 +820,10 @@ int orc_step(orc_sim* s, int nsteps) {
     /* advance the state: masks, stranded flags, volumes of dissolved nodes */
     for (int i = 0; i < N; ++i) {
       const int told = s->type[i], tnew = s->tnext[i];
-      uint8_t lq = 0;
-      if (tnew == ORC_FLUID) {
-        const double r1 = (told == ORC_FLUID) ? s->rho[i] : s->rbar[i];
-        lq = r1 > thr;
-      }
       if (told == ORC_FLUID && tnew == ORC_SOLID_F) s->led.n_precipitated += 1.0;
       if (told != ORC_FLUID && tnew == ORC_FLUID) s->V[i] = 0.0;
       s->stranded[i] = (told == ORC_FLUID && tnew == ORC_SOLID_F);
-      s->liqprev[i] = s->liq[i];
-      s->liq[i] = lq;
+      s->sflag[i] = s->snext[i];
       s->type[i] = (uint8_t)tnew;
     }
     double* t;
@@ -804,6 +844,7 @@ void orc_fields(orc_sim* s, double* rho1, double* rho2, double* ux, double* uy,
    * it may count psi clamps; keep the ledger as it was */
   orc_ledger keep = s->led;
   macros(s);
+  mark_liquid(s);
   s->led = keep;
   for (int i = 0; i < N; ++i) {
     if (rho1) rho1[i] = s->rho[i];
@@ -814,9 +855,17 @@ void orc_fields(orc_sim* s, double* rho1, double* rho2, double* ux, double* uy,
     if (liquid) liquid[i] = s->liq[i];
     if (V) V[i] = s->V[i];
   }
+  /* solute content after the shares in transit are delivered: a node holding
+   * a share in transit reports none, its receivers report it */
   if (C)
     for (int k = 0; k < s->ns; ++k)
-      for (int i = 0; i < N; ++i) C[k * N + i] = s->C[k * N + i];
+      for (int i = 0; i < N; ++i) {
+        const int sf = s->sflag[i];
+        double c = 0.0;
+        if (sf == SF_STREAM) c = s->C[k * N + i] + s->Cin[k * N + i];
+        else if (sf == SF_HOLD) c = s->C[k * N + i];
+        C[k * N + i] = c;
+      }
   if (ledger) *ledger = s->led;
   if (rho_max_prev) *rho_max_prev = s->rho_max_prev;
 }
@@ -827,5 +876,5 @@ void orc_state(orc_sim* s, double* f, double* g, uint8_t* flags) {
   if (g) memcpy(g, s->g, sizeof(double) * 5 * (size_t)s->ns * N);
   if (flags)
     for (int i = 0; i < N; ++i)
-      flags[i] = (uint8_t)(s->liq[i] | (s->liqprev[i] << 1) | (s->stranded[i] << 2));
+      flags[i] = (uint8_t)(s->sflag[i] | (s->stranded[i] << 2));
 }

@@ -80,7 +80,8 @@ typedef struct {
   double mass_rem[2];   /* stranded mass with no fluid neighbour to take it */
   double sol_src[ORC_MAX_SPECIES];  /* sum of homogeneous solute sources (Eq. 28) */
   double sol_het[ORC_MAX_SPECIES];  /* net heterogeneous boundary exchange (Eq. 29-31) */
-  double sol_rem[ORC_MAX_SPECIES];  /* solute with no liquid neighbour to take it */
+  double sol_rem[ORC_MAX_SPECIES];  /* solute dropped: always 0 (content without a liquid
+                                       neighbour is kept until it has one) */
   double vol_dv;        /* sum of all VOP volume increments (Eq. 33, 35) */
   double vol_clip;      /* sum of the (non-positive) volumes of removed solid nodes */
   double n_psi_clamp;   /* count of clamped negative psi arguments */
@@ -98,12 +99,16 @@ orc_sim* orc_create(const orc_params* p, const uint8_t* type0, const double* V0,
                     char* err, int errlen);
 /* Advances n steps; returns 0, or -1 on instability (message in orc_error). */
 int orc_step(orc_sim* s, int n);
-/* Macroscopic fields of the current state.  Any pointer may be NULL. */
+/* Macroscopic fields of the current state.  Any pointer may be NULL.
+ * liquid: this step's liquid marks (Sec. 4.5).  C: the solute each node holds
+ * once the shares in transit are delivered. */
 void orc_fields(orc_sim* s, double* rho1, double* rho2, double* ux, double* uy,
                 double* C, uint8_t* type, uint8_t* liquid, double* V,
                 orc_ledger* ledger, double* rho_max_prev);
 /* Raw state (populations, flags) for brute-force cross-checks.  Any pointer may be NULL.
- * f: 2*9*N, g: ns*5*N, flags: N bytes (bit0 liquid(n), bit1 liquid(n-1), bit2 stranded). */
+ * f: 2*9*N, g: ns*5*N, flags: N bytes (bits 0-1 the solute a node holds: 0 none,
+ * 1 streamed populations (liquid last step), 2 content kept at rest, 3 shares in
+ * transit; bit 2 stranded). */
 void orc_state(orc_sim* s, double* f, double* g, uint8_t* flags);
 const char* orc_error(orc_sim* s);
 int64_t orc_step_count(orc_sim* s);

@@ -44,6 +44,84 @@ def test_poiseuille_profile(H, tau, tol):
 
 
 # --------------------------------------------------------------------------
+# Flow: momentum of the two-component system (Eq. 14, 17-19)
+# --------------------------------------------------------------------------
+EX9 = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
+EY9 = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
+
+
+def _population_momentum(sim):
+    """Total momentum sum_x sum_sigma sum_a f e_a of the streamed populations."""
+    f, _, _ = sim.state()
+    return np.array([np.einsum("sayx,a->", f, EX9), np.einsum("sayx,a->", f, EY9)])
+
+
+def _two_component_box(tau2, gbody):
+    """A periodic 48 x 32 box with no solid: the liquid component of the
+    modified EOS set above its critical temperature (1.5 T_c, so no phase
+    boundary limits the time step) with a smooth dense blob (1 to 3) and the
+    gas component with a blob of its own elsewhere (1 to 1.5), seeded noise,
+    G12 = G21 = 0.3, tau_1 = 1 and tau_2 as given.  rho10 = 3, rho20 = 1 and
+    a0 = 0.5 keep both effective masses of Eq. 15 varying across the box
+    (with the workloads' values both saturate, phi_1 near 1 and phi_2 near a0,
+    and the pair force nearly vanishes)."""
+    a, b, R = W.EOS_PAPER
+    nx, ny = 48, 32
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    r1 = np.sqrt((xx - 20.3) ** 2 + (yy - 15.6) ** 2)
+    r2 = np.sqrt((xx - 33.1) ** 2 + (yy - 20.4) ** 2)
+    rng = np.random.default_rng(7)
+    rho1 = 1.0 + 2.0 * np.exp(-(r1 / 6.0) ** 2) + rng.uniform(-1e-2, 1e-2, (ny, nx))
+    rho2 = 1.0 + 0.5 * np.exp(-(r2 / 5.0) ** 2) + rng.uniform(-1e-2, 1e-2, (ny, nx))
+    p = W.uniform_problem(nx, ny, ideal=False, a=a, b=b, R=R, T=1.5 * W.critical_temperature(a, b, R),
+                          G11=-1.0, G12=0.3, G21=0.3, rho10=3.0, rho20=1.0, a0=0.5,
+                          tau=(1.0, tau2), gbody=gbody)
+    return p.copy(rho1=rho1, rho2=rho2, name="momentum-box")
+
+
+@pytest.mark.parametrize("tau2", [0.8, 1.3])
+def test_momentum_conserved_with_unequal_relaxation(tau2):
+    """With no wall and no body force the collision of Eq. 6 with the
+    equilibrium velocities of Eq. 17-18 returns sum_sigma rho_sigma u_eq / tau
+    = sum_sigma j_sigma / tau + F_sigma, so each step changes the total
+    momentum by the total force; the cohesion of Eq. 11 and the pair force of
+    Eq. 14 with G12 = G21 cancel over a periodic lattice (each link's two ends
+    feel opposite forces).  The total momentum of the populations therefore
+    stays at its initial zero to round-off while the blobs spread, for
+    tau_1 != tau_2.  A density-weighted common velocity, swapped
+    relaxation times in the shift, an unbalanced sign in either half of the
+    pair force or the wrong effective mass in it breaks this."""
+    p = _two_component_box(tau2, (0.0, 0.0))
+    s = OracleSim(p)
+    M = p.rho1.sum() + p.rho2.sum()
+    P0 = _population_momentum(s)
+    assert np.abs(P0).max() < 1e-12 * M
+    moved = 0.0
+    for _ in range(40):
+        s.step(5)
+        P = _population_momentum(s)
+        assert np.abs(P - P0).max() < 1e-13 * M, P - P0
+        F = s.fields()
+        moved = max(moved, np.abs(F["ux"]).max(), np.abs(F["uy"]).max())
+    assert moved > 1e-4   # the fluid is not at rest
+
+
+def test_momentum_grows_by_body_force():
+    """With a body acceleration g (forces rho_sigma g added before Eq. 17-19)
+    the total momentum grows by g times the (conserved) total mass every
+    step, again with tau_1 != tau_2."""
+    g = np.array([2e-6, -1e-6])
+    p = _two_component_box(0.8, tuple(g))
+    s = OracleSim(p)
+    M = p.rho1.sum() + p.rho2.sum()
+    P0 = _population_momentum(s)
+    for n in range(1, 101):
+        s.step(1)
+        P = _population_momentum(s)
+        assert np.allclose(P - P0, n * g * M, rtol=1e-10, atol=1e-13 * M), (n, P - P0, n * g * M)
+
+
+# --------------------------------------------------------------------------
 # Flow: liquid-vapour coexistence (text after Eq. 13; Sec. 5.1)
 # --------------------------------------------------------------------------
 def _flat_interface(eos, Tr, rl, rv, psi_literal=False, ny=128, steps=16000):
