@@ -50,20 +50,32 @@ __host__ __device__ constexpr double wf(int a) { return a == 0 ? 0.0 : (a < 5 ? 
 static_assert(opp(1) == 3 && opp(2) == 4 && opp(3) == 1 && opp(4) == 2, "opp axes");
 static_assert(opp(5) == 7 && opp(6) == 8 && opp(7) == 5 && opp(8) == 6, "opp diagonals");
 
-// Node status word (32 bits): bits 0-1 type, bit 2 liquid this step, bit 3
-// liquid last step, bit 4 stranded (became SOLID_F at the end of the last step;
+// Node status word (32 bits): bits 0-1 type, bits 2-3 the solute the node
+// holds (SF_*), bit 4 stranded (became SOLID_F at the end of the last step;
 // its incoming populations are still to be pulled and given away), bits 8-15
 // neighbour b = 1..8 was fluid last step, bits 16-19 D2Q5 neighbour b = 1..4 was
-// liquid last step.  A node with none of bits 8-19 set reads its own slots
-// back; that is how the initial state and a node freed by dissolution (both
-// at rest, whose populations are equal in opposite directions) enter the pull.
-// Bit 7 marks "outside a non-periodic boundary" in the kernel only.
-constexpr uint32_t TB_T = 0x3, TB_LIQ = 0x4, TB_LIQP = 0x8, TB_STR = 0x10, TB_WALL = 0x80;
-constexpr int NBF_SHIFT = 8, NBL_SHIFT = 16;
+// liquid last step (set at liquid nodes only).  A node with none of bits 8-19
+// set reads its own slots back; that is how the initial state, a node freed by
+// dissolution (both at rest, whose populations are equal in opposite
+// directions) and a node keeping solute at rest enter the pull.  Bit 7 marks
+// "outside a non-periodic boundary" in the kernel only.
+constexpr uint32_t TB_T = 0x3, TB_SF = 0xC, TB_STR = 0x10, TB_WALL = 0x80;
+constexpr int NBF_SHIFT = 8, NBL_SHIFT = 16, SF_SHIFT = 2;
+// Solute a node holds at the start of a step (Sec. 4.5 amendments):
+//   SF_STREAM  liquid in the previous step: its slots get the populations
+//              streamed into it
+//   SF_HOLD    not liquid; keeps its content at rest in its own slots (it had
+//              no liquid D2Q5 neighbour to give it to)
+//   SF_SHARE   left the liquid set last step; its own slots hold, at rest, one
+//              equal share of its content per D2Q5 neighbour that was liquid
+//              then, which those neighbours take during this step
+enum { SF_NONE = 0, SF_STREAM = 1, SF_HOLD = 2, SF_SHARE = 3 };
+__host__ __device__ inline int sf_of(uint32_t w) { return (int)((w & TB_SF) >> SF_SHIFT); }
 
-// 16-bit population storage keeps each population as a deviation from w_a
-// times a reference density of the node that will pull it (flow) or J_a
-// times a reference concentration (solute).  A reference is coded in a few
+// FP32 and 16-bit population storage keep each flow population as a
+// deviation from w_a times a reference density of the node that will pull it
+// (FP32 divides the deviation by w_a; 16-bit storage also keeps solute as a
+// deviation from J_a times a reference concentration).  A reference is coded in a few
 // bits: the float's bit pattern above bit `sh` (exponent and top mantissa
 // bits), counted from a base, and decoded to the middle of its bucket.  The
 // codes are integer operations on both sides, so the writer of a population
@@ -95,12 +107,14 @@ constexpr int T_FLUID = 0, T_INERT = 1, T_D = 2, T_F = 3;
 constexpr int L_MSRC = 0, L_MINJ = 2, L_MREM = 4, L_SSRC = 6, L_SHET = 14, L_SREM = 22, L_VDV = 30,
               L_VCLIP = 31, L_CLAMP = 32, L_NDIS = 33, L_NPRE = 34, L_NL2G = 35, L_NG2L = 36;
 constexpr int NLED = 38;  // + steps (host)
-// LDS slots of the rarely non-zero balances: 0-1 mass_inj, 2-3 mass_rem, 4 vol_clip,
-// 5 psi clamps, 6 dissolved, 7 precipitated, 8-15 sol_rem, 16 liquid->gas, 17 gas->liquid
-constexpr int NRARE_SLOTS = 18;
+// LDS slots of the rarely non-zero balances (a wavefront's sums, added by
+// lane 0 in row order): 0-1 mass_inj, 2-3 mass_rem, 4 vol_clip, 5 psi clamps,
+// 6 dissolved, 7 precipitated, 8 liquid->gas, 9 gas->liquid.  Solute is never
+// dropped, so sol_rem stays zero.
+constexpr int NRARE_SLOTS = 10;
 __host__ __device__ constexpr int rare_dst(int i) {
   return i == 0 ? L_MINJ : i == 1 ? L_MINJ + 1 : i == 2 ? L_MREM : i == 3 ? L_MREM + 1 : i == 4 ? L_VCLIP
-       : i == 5 ? L_CLAMP : i == 6 ? L_NDIS : i == 7 ? L_NPRE : i < 16 ? L_SREM + (i - 8) : i == 16 ? L_NL2G : L_NG2L;
+       : i == 5 ? L_CLAMP : i == 6 ? L_NDIS : i == 7 ? L_NPRE : i == 8 ? L_NL2G : L_NG2L;
 }
 
 // rho_max slots: 3 rotating step slots x 8 partial maxima (one per XCD), each
@@ -119,7 +133,7 @@ struct KConst {
   int ncw;                                  // solute code words per node (16-bit storage)
   int sg;                                   // species per solute slot (species_group)
   long long plane;
-  double om[2], tau[2], RT, a, b, G11, psi_pre, G12, G21, w1, w2, gx, gy, a0, rho10, rho20, lfrac;
+  double om[2], tau[2], RT, a, b, G11, rG11, psi_pre, G12, G21, w1, w2, gx, gy, a0, rho10, rho20, lfrac;
   int has_psi, has_phi1, has_phi2;
   double J[LBRX_MAX_SPECIES][5];
   double omg[LBRX_MAX_SPECIES];
@@ -144,6 +158,9 @@ template <typename T> struct KT {
       r_hMgas[LBRX_MAX_RXN];
   T xkap[LBRX_MAX_RXN], xCeq[LBRX_MAX_RXN];
   T hnu[LBRX_MAX_RXN][LBRX_MAX_SPECIES];  // net stoichiometric coefficient of species k in reaction r
+  // FP32 solute weights of Eq. 22 as stored: J1' on a 2^-26 grid and
+  // J0' = 1 - 4 J1', so that the weights sum to one exactly; 1 / (2 J1'), 1 / J1'
+  T Jp0[LBRX_MAX_SPECIES], Jp1[LBRX_MAX_SPECIES], hJ[LBRX_MAX_SPECIES], iJ1[LBRX_MAX_SPECIES];
   // 16-bit storage: deviation scales (powers of two) and reference-code bases
   T sc[2], isc[2], wsc[2][3];               // flow: scale, 1/scale, w (rest, axis, diagonal) x scale
   T scg[LBRX_MAX_SPECIES], iscg[LBRX_MAX_SPECIES], Jsc[LBRX_MAX_SPECIES][2];
@@ -165,7 +182,7 @@ template <typename T> struct KArgs {
   unsigned long long* rmax;  // 3 rotating slots
   double* led;               // [nitems][NLED]
   unsigned int* err;         // [0] flags, [1] first failing node (min index)
-  double *o_r1, *o_r2, *o_ux, *o_uy, *o_C;  // export outputs (plane-sized)
+  double *o_r1, *o_r2, *o_ux, *o_uy, *o_C, *o_L;  // export outputs (plane-sized); o_L: liquid marks
 };
 
 // constant address space: data no store of a running kernel can change
@@ -350,20 +367,24 @@ template <typename T> struct alignas(2 * sizeof(T)) RF {
 
 template <typename T, int NS, int SM> struct WaveLds {
   static constexpr int NSA = NS > 0 ? NS : 1;
-  static constexpr int NRF = sm_dev(SM) ? 3 : 1;  // reference rows (16-bit storage only)
-  static constexpr int NHF = sm_dev(SM) ? 2 : 1;
+  // flow reference rows (FP32 and 16-bit storage), solute reference rows (16-bit storage)
+  static constexpr bool REFS = sm_dev(SM) || std::is_same<T, float>::value;
+  static constexpr int NRF = REFS ? 3 : 1;
+  static constexpr int NHF = REFS ? 2 : 1;
+  static constexpr int NCF = sm_dev(SM) ? 3 : 1;
+  static constexpr int NHC = sm_dev(SM) ? 2 : 1;
   // ring rows (R - 1, R, R + 1 in rotation) x columns x0 - 1 .. x0 + 64
   PQ<T> pq[3][SW + 2];
   T r1[3][SW + 2], r2[3][SW + 2];
   T C[NSA][3][SW + 2];
   RF<T> rf[NRF][SW + 2];
-  T Cf[NSA][NRF][SW + 2];
+  T Cf[NSA][NCF][SW + 2];
   // halo columns (left, right) for rows y0 - 1 .. y0 + H
   PQ<T> hpq[2][HMAX + 2];
   T hr1[2][HMAX + 2], hr2[2][HMAX + 2];
   T hC[NSA][2][HMAX + 2];
   RF<T> hrf[NHF][HMAX + 2];
-  T hCf[NSA][NHF][HMAX + 2];
+  T hCf[NSA][NHC][HMAX + 2];
   double rare[NRARE_SLOTS];
 };
 
@@ -463,7 +484,18 @@ template <typename ST, int SG> __device__ inline void bstoreg(const Grp<ST, SG>&
 
 template <typename T, int NS> struct Mom {
   T rho[2], jx[2], jy[2], C[NS > 0 ? NS : 1];
+  T drho[2];  // FP32 storage: rho - the decoding reference (the mass the deviations carry)
 };
+
+// deterministic sum over the wavefront (a fixed butterfly; lane 0's result)
+__device__ inline double wave_sum_det(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return __builtin_bit_cast(double, ((unsigned long long)__builtin_amdgcn_readfirstlane(
+                                         (unsigned)(__builtin_bit_cast(unsigned long long, v) >> 32)) << 32) |
+                                        (unsigned)__builtin_amdgcn_readfirstlane(
+                                            (unsigned)__builtin_bit_cast(unsigned long long, v)));
+}
 
 template <typename T, int SM, int NS, bool EXPORT>
 __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchArgs LA_arg) {
@@ -509,6 +541,12 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
   using ST = typename StoreT<T, SM>::type;  // stored population type
   constexpr unsigned ES = sizeof(ST);
   constexpr bool DEV = sm_dev(SM);
+  // FP32 storage: a flow slot holds s_a = f_a / w_a - R (R the reader's
+  // reference density) and a solute slot g_a / J'_a, and the arithmetic works
+  // on these (mass carried by the small deviations, weights that sum to one
+  // exactly), so that rounding does not drift the balances step after step
+  constexpr bool SFORM = std::is_same<T, float>::value && !DEV;
+  constexpr bool REFS = DEV || SFORM;  // flow reference codes in the status words
   // this simulation's top side is a free outlet (only in SM_OUT kernels; a
   // batch of mixed simulations runs them all in one)
   const bool outy = SM == SM_OUT && A.c.per_y == 2;
@@ -551,34 +589,54 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
   auto is_fluid = [](uint32_t v) { return (v & LF_FLU) != 0; };
   auto is_liq = [](uint32_t v) { return (v & LF_LIQN) != 0; };
   auto is_rsolid = [](uint32_t v) { return !(v & TB_WALL) && (v & TB_T) >= T_D; };
-  // LDS flags of an in-domain node's status word
-  auto flags_w = [](uint32_t w) -> uint32_t {
-    return (w & 0x1fu) | ((w & TB_T) == T_FLUID ? LF_FLU : 0u) | (((w & TB_T) == T_FLUID && (w & TB_LIQ)) ? LF_LIQN : 0u);
-  };
+  // LDS flags of an in-domain node's status word; its liquid mark of this step
+  // is added where its density is known
+  auto flags_w = [](uint32_t w) -> uint32_t { return (w & 0x1fu) | ((w & TB_T) == T_FLUID ? LF_FLU : 0u); };
+
+  // Liquid threshold of this step (Sec. 4.5): liquid_frac times the largest
+  // liquid-component density of the previous step (the partial maxima of its
+  // slot; the current step's is known only once every node is updated).
+  double rprev = 0.0;
+#pragma unroll
+  for (int xc = 0; xc < 8; ++xc)
+    rprev = fmax(rprev, __longlong_as_double((long long)A.rmax[slot_prev * RM_SLOT + xc * RM_STRIDE]));
+  const double thr = c.lfrac * rprev;
 
   // status word of node (X, Y), TB_WALL outside a non-periodic side
   auto word_at = [&](int X, int Y) -> uint32_t {
     if (wrap(X, nx, c.per_x) && wrap_y(Y)) return bload<uint32_t>(rt, (unsigned)X * 4u, (unsigned)Y * upitch * 4u);
     return TB_WALL;
   };
+  // the flow references a node decodes its pulled populations with (FP32 and
+  // 16-bit storage): coded in its status word when they were written
+  auto refs_of = [&](uint32_t w, T& r1, T& r2) {
+    if constexpr (REFS) {
+      r1 = ref_value(code1_of(w), k.rb1, SH1);
+      r2 = ref_value(code2_of(w), k.rb2, SH2);
+    } else {
+      r1 = r2 = T(0);
+    }
+  };
 
   // Pull (streaming of the previous step): population a arrives from
   // x - e_a = x + e_b (b = opp(a)) if that node was fluid (liquid) then,
   // otherwise it is this node's own population b bounced back at the halfway
   // wall.  co[] are the byte offsets of columns x-1, x, x+1 (wrapped); Yw is
-  // the wrapped row of an in-domain node.
-  auto pull = [&](const unsigned (&co)[3], int Yw, uint32_t w, bool validf, bool liqp, T(&f)[2][9], T(&g)[NSA][5]) {
+  // the wrapped row of an in-domain node.  withg: the node holds solute.
+  auto pull = [&](const unsigned (&co)[3], int Yw, uint32_t w, bool validf, bool withg, T(&f)[2][9], T(&g)[NSA][5]) {
     // (beyond a wall the neighbour bit is clear and the row is never read;
     // beyond the outlet the ghost row is row ny - 1 itself)
     int ym = Yw - 1, yp = Yw + 1;
     if (ym < 0) ym += ny;
     if (yp >= ny) yp = outy ? ny - 1 : yp - ny;
     const unsigned ur[3] = {(unsigned)ym, (unsigned)Yw, (unsigned)yp};
-    // a stored value becomes a population: itself, or (16-bit storage)
-    // deviation / scale + weight x this node's reference
+    // a stored value becomes a population: itself (FP64; FP32 keeps the
+    // normalised deviation), or (16-bit storage) deviation / scale + weight x
+    // this node's reference
     T fb[2][3];
     if constexpr (DEV) {
-      const T r1 = ref_value(code1_of(w), k.rb1, SH1), r2 = ref_value(code2_of(w), k.rb2, SH2);
+      T r1, r2;
+      refs_of(w, r1, r2);
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
         fb[0][q] = k.wc[q] * r1;
@@ -615,8 +673,28 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
         const bool src = (w >> (NBF_SHIFT + b - 1)) & 1u;
         fin(a, src ? co[ex(b) + 1] + (ur[ey(b) + 1] * RSF + (unsigned)a * PS) : own + (unsigned)b * PS);
       }
+      if constexpr (SFORM) {
+        // Free outlet: the downward populations of the top row have two
+        // readers (the row below, and the top row through the ghost row), so
+        // they are stored with reference zero; re-reference them here
+        if (outy && Yw >= ny - 2) {
+          T r1, r2;
+          refs_of(w, r1, r2);
+#pragma unroll
+          for (int b = 1; b < 9; ++b) {
+            const int a = opp(b);
+            const bool src = (w >> (NBF_SHIFT + b - 1)) & 1u;
+            // the value read is slot a of the row above (pulled), or own slot b
+            const bool zref = src ? (ey(a) < 0) : (ey(b) < 0 && Yw == ny - 1);
+            if (zref) {
+              f[0][a] -= r1;
+              f[1][a] -= r2;
+            }
+          }
+        }
+      }
     }
-    if (NS > 0 && liqp) {
+    if (NS > 0 && withg) {
       const unsigned own = (co[1] << GSH) + ur[1] * RSG;
       T gb[NSA][2];
       if constexpr (DEV) {
@@ -663,26 +741,49 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
   };
 
   // moments (Eq. 9, 23); terms with a zero velocity component are skipped:
-  // adding +-0 to the running sum would not change it
-  auto moments = [&](const T(&f)[2][9], const T(&g)[NSA][5], Mom<T, NS>& m) {
+  // adding +-0 to the running sum would not change it.  FP32 storage: the
+  // deviations s_a = f_a / w_a - R give rho - R = sum w_a s_a and j = sum w_a
+  // s_a e_a (the w_a are 16, 4 and 1 over 36); solute C = J0' t_0 + J1' (t_1 +
+  // .. + t_4) with t_a = g_a / J'_a.
+  auto moments = [&](const T(&f)[2][9], const T(&g)[NSA][5], uint32_t w, bool validf, Mom<T, NS>& m) {
+    if constexpr (SFORM) {
+      T r[2] = {T(0), T(0)};  // a node without flow populations has none
+      if (validf) refs_of(w, r[0], r[1]);
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      m.rho[s] = T(0);
-      m.jx[s] = T(0);
-      m.jy[s] = T(0);
-#pragma unroll
-      for (int a = 0; a < 9; ++a) {
-        m.rho[s] += f[s][a];
-        if (ex(a) != 0) m.jx[s] += f[s][a] * T(ex(a));
-        if (ey(a) != 0) m.jy[s] += f[s][a] * T(ey(a));
+      for (int s = 0; s < 2; ++s) {
+        const T ax = ((f[s][1] + f[s][2]) + f[s][3]) + f[s][4];
+        const T dg = ((f[s][5] + f[s][6]) + f[s][7]) + f[s][8];
+        m.drho[s] = (T(16) * f[s][0] + T(4) * ax + dg) * T(1.0 / 36.0);
+        m.rho[s] = r[s] + m.drho[s];
+        m.jx[s] = (T(4) * (f[s][1] - f[s][3]) + ((f[s][5] - f[s][6]) - f[s][7] + f[s][8])) * T(1.0 / 36.0);
+        m.jy[s] = (T(4) * (f[s][2] - f[s][4]) + ((f[s][5] + f[s][6]) - f[s][7] - f[s][8])) * T(1.0 / 36.0);
       }
-    }
 #pragma unroll
-    for (int kk = 0; kk < NSA; ++kk) {
-      T cs = T(0);
+      for (int kk = 0; kk < NSA; ++kk)
+        m.C[kk] = k.Jp0[kk] * g[kk][0] + k.Jp1[kk] * (((g[kk][1] + g[kk][2]) + g[kk][3]) + g[kk][4]);
+    } else {
+      (void)w;
+      (void)validf;
 #pragma unroll
-      for (int a = 0; a < 5; ++a) cs += g[kk][a];
-      m.C[kk] = cs;
+      for (int s = 0; s < 2; ++s) {
+        m.rho[s] = T(0);
+        m.jx[s] = T(0);
+        m.jy[s] = T(0);
+        m.drho[s] = T(0);
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+          m.rho[s] += f[s][a];
+          if (ex(a) != 0) m.jx[s] += f[s][a] * T(ex(a));
+          if (ey(a) != 0) m.jy[s] += f[s][a] * T(ey(a));
+        }
+      }
+#pragma unroll
+      for (int kk = 0; kk < NSA; ++kk) {
+        T cs = T(0);
+#pragma unroll
+        for (int a = 0; a < 5; ++a) cs += g[kk][a];
+        m.C[kk] = cs;
+      }
     }
   };
 
@@ -693,12 +794,27 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
     if (fluid) {
       if (c.has_psi) {
         if (!(T(0.25) * k.b * rho[0] < T(1))) errf |= ERR_EOS;
-        T arg = cdiv<T>(k.psi_pre * (p_cs<T>(k, rho[0]) - cdiv<T>(rho[0], T(3), T(1.0 / 3.0))), k.G11, k.r_G11);
-        if (arg < T(0)) {
-          arg = T(0);
-          clamped = true;
+        if constexpr (SFORM) {
+          // FP32 storage: the two terms of Eq. 12 nearly cancel in the liquid
+          // (the pressure is a few hundredths of each), so the argument is
+          // formed in FP64; its square root in FP32
+          const double r0 = (double)rho[0];
+          const double e = 0.25 * c.b * r0, om = 1.0 - e;
+          const double pcs = r0 * c.RT * (1.0 + e + e * e - e * e * e) / (om * om * om) - c.a * r0 * r0;
+          double arg = c.psi_pre * (pcs - r0 * (1.0 / 3.0)) * c.rG11;
+          if (arg < 0.0) {
+            arg = 0.0;
+            clamped = true;
+          }
+          ps = dsqrt<T>((T)arg);
+        } else {
+          T arg = cdiv<T>(k.psi_pre * (p_cs<T>(k, rho[0]) - cdiv<T>(rho[0], T(3), T(1.0 / 3.0))), k.G11, k.r_G11);
+          if (arg < T(0)) {
+            arg = T(0);
+            clamped = true;
+          }
+          ps = dsqrt<T>(arg);
         }
-        ps = dsqrt<T>(arg);
       }
       if (c.has_phi1) q1 = T(1) - dexp<T>(-cdiv<T>(rho[1], k.rho20, k.r_rho20));
       if (c.has_phi2) q2 = k.a0 - dexp<T>(-cdiv<T>(rho[0], k.rho10, k.r_rho10));
@@ -709,9 +825,11 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
   // written this step (from the current moments; stored in its status and
   // solute words for the reader)
   auto wref = [&](const Mom<T, NS>& m, RF<T>& r, T(&cf)[NSA]) {
-    if constexpr (DEV) {
+    if constexpr (REFS) {
       r.r1 = ref_value(ref_code(m.rho[0], k.rb1, SH1, MAX1), k.rb1, SH1);
       r.r2 = ref_value(ref_code(m.rho[1], k.rb2, SH2, MAX2), k.rb2, SH2);
+    }
+    if constexpr (DEV) {
 #pragma unroll
       for (int kk = 0; kk < NSA; ++kk) cf[kk] = ref_value(ref_code(m.C[kk], k.rbc[kk], SHC, MAXC), k.rbc[kk], SHC);
     }
@@ -736,30 +854,33 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
     const int t = (int)(hw & TB_T);
     const bool fluid = indom && t == T_FLUID;
     const bool validf = indom && (t == T_FLUID || (hw & TB_STR));
-    const bool liqp = indom && (hw & TB_LIQP);
+    const bool withg = indom && sf_of(hw) != SF_NONE;
     unsigned co[3];
     col_offsets(indom ? HX : 0, co);
     T f[2][9], g[NSA][5];
-    pull(co, indom ? HY : 0, hw, validf, liqp, f, g);
+    pull(co, indom ? HY : 0, hw, validf, withg, f, g);
     Mom<T, NS> m;
-    moments(f, g, m);
+    moments(f, g, hw, validf, m);
     T ps, q1, q2;
     bool cl;
     unsigned ef = 0;
     effmass(fluid, m.rho, ps, q1, q2, cl, ef);
     if (hact) {
-      L.hpq[hs][hr] = PQ<T>{ps, q1, q2, flags_as<T>(indom ? flags_w(hw) : (uint32_t)TB_WALL)};
+      const uint32_t fl = indom ? (flags_w(hw) | ((fluid && (double)m.rho[0] > thr) ? LF_LIQN : 0u)) : (uint32_t)TB_WALL;
+      L.hpq[hs][hr] = PQ<T>{ps, q1, q2, flags_as<T>(fl)};
       L.hr1[hs][hr] = m.rho[0];
       L.hr2[hs][hr] = m.rho[1];
 #pragma unroll
       for (int kk = 0; kk < NSA; ++kk) L.hC[kk][hs][hr] = m.C[kk];
-      if constexpr (DEV) {
+      if constexpr (REFS) {
         RF<T> r;
         T cf[NSA];
         wref(m, r, cf);
         L.hrf[hs][hr] = r;
+        if constexpr (DEV) {
 #pragma unroll
-        for (int kk = 0; kk < NSA; ++kk) L.hCf[kk][hs][hr] = cf[kk];
+          for (int kk = 0; kk < NSA; ++kk) L.hCf[kk][hs][hr] = cf[kk];
+        }
       }
     }
   }
@@ -772,18 +893,15 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
   unsigned co[3];
   col_offsets(colin ? Xw : 0, co);
 
-  // per-lane balance contributions over the item's rows
-  T l_msrc[2] = {T(0), T(0)};
-  T l_ssrc[NSA], l_shet[NSA];
+  // per-lane balance contributions over the item's rows, in FP64: the gas
+  // component's homogeneous source (the liquid component's is its exact
+  // negative), the solute sources and the heterogeneous exchange
+  double l_msrc = 0.0;
+  double l_ssrc[NSA], l_shet[NSA];
 #pragma unroll
-  for (int kk = 0; kk < NSA; ++kk) l_ssrc[kk] = l_shet[kk] = T(0);
+  for (int kk = 0; kk < NSA; ++kk) l_ssrc[kk] = l_shet[kk] = 0.0;
   double l_vdv = 0.0;
   T my_rmax = T(0);
-  double rprev = 0.0;
-#pragma unroll
-  for (int xc = 0; xc < 8; ++xc)
-    rprev = fmax(rprev, __longlong_as_double((long long)A.rmax[slot_prev * RM_SLOT + xc * RM_STRIDE]));
-  const double thr = c.lfrac * rprev;
 
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 
@@ -812,35 +930,40 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
       const int t = (int)(w & TB_T);
       const bool fluid = indom && t == T_FLUID;
       const bool validf = indom && (t == T_FLUID || (w & TB_STR));
-      const bool liqp = indom && (w & TB_LIQP);
-      pull(co, rowin ? Yw : 0, w, validf, liqp, fn, gn);
-      moments(fn, gn, mn);
+      const bool withg = indom && sf_of(w) != SF_NONE;
+      pull(co, rowin ? Yw : 0, w, validf, withg, fn, gn);
+      moments(fn, gn, w, validf, mn);
       unsigned errf = 0;
       if (validf && (!(mn.rho[0] >= T(0)) || !(mn.rho[1] >= T(0)) || (fluid && !(mn.rho[0] + mn.rho[1] > T(0)))))
         errf |= ERR_DENSITY;
       T ps, q1, q2;
       bool clamped;
       effmass(fluid, mn.rho, ps, q1, q2, clamped, errf);
-      if (!EXPORT && colown && Rn >= y0 && Rn < y1) {
-        if (errf) {
-          atomicOr(&A.err[0], errf);
-          atomicMin(&A.err[1], (unsigned)(Rn * nx + X));
-        }
-        if (clamped) atomicAdd(&L.rare[5], 1.0);
+      const bool mine = !EXPORT && colown && Rn >= y0 && Rn < y1;
+      if (mine && errf) {
+        atomicOr(&A.err[0], errf);
+        atomicMin(&A.err[1], (unsigned)(Rn * nx + X));
+      }
+      if (!EXPORT) {
+        const unsigned long long bc = __ballot(mine && clamped);
+        if (bc && lane == 0) L.rare[5] += (double)__popcll(bc);
       }
       const int cl = lane + 1;
-      L.pq[sp][cl] = PQ<T>{ps, q1, q2, flags_as<T>(indom ? flags_w(w) : (uint32_t)TB_WALL)};
+      const uint32_t fl = indom ? (flags_w(w) | ((fluid && (double)mn.rho[0] > thr) ? LF_LIQN : 0u)) : (uint32_t)TB_WALL;
+      L.pq[sp][cl] = PQ<T>{ps, q1, q2, flags_as<T>(fl)};
       L.r1[sp][cl] = mn.rho[0];
       L.r2[sp][cl] = mn.rho[1];
 #pragma unroll
       for (int kk = 0; kk < NSA; ++kk) L.C[kk][sp][cl] = mn.C[kk];
-      if constexpr (DEV) {
+      if constexpr (REFS) {
         RF<T> r;
         T cf[NSA];
         wref(mn, r, cf);
         L.rf[sp][cl] = r;
+        if constexpr (DEV) {
 #pragma unroll
-        for (int kk = 0; kk < NSA; ++kk) L.Cf[kk][sp][cl] = cf[kk];
+          for (int kk = 0; kk < NSA; ++kk) L.Cf[kk][sp][cl] = cf[kk];
+        }
       }
       if (lane < 2) {
         const int ce = lane ? SW + 1 : 0;
@@ -850,10 +973,12 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
         L.r2[sp][ce] = L.hr2[lane][hr];
 #pragma unroll
         for (int kk = 0; kk < NSA; ++kk) L.C[kk][sp][ce] = L.hC[kk][lane][hr];
-        if constexpr (DEV) {
+        if constexpr (REFS) {
           L.rf[sp][ce] = L.hrf[lane][hr];
+          if constexpr (DEV) {
 #pragma unroll
-          for (int kk = 0; kk < NSA; ++kk) L.Cf[kk][sp][ce] = L.hCf[kk][lane][hr];
+            for (int kk = 0; kk < NSA; ++kk) L.Cf[kk][sp][ce] = L.hCf[kk][lane][hr];
+          }
         }
       }
     }
@@ -865,8 +990,7 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
       const int t = (int)(w & TB_T);
       const bool own = colown;  // R < y1 <= ny
       const bool fluid = colin && t == T_FLUID;
-      const bool liq = colin && (w & TB_LIQ);
-      const bool liqp = colin && (w & TB_LIQP);
+      const int sf = colin ? sf_of(w) : SF_NONE;
       const unsigned idx = (unsigned)R * upitch + (unsigned)X;
       auto slot = [&](int dy) { return dy < 0 ? sm : (dy > 0 ? sp : s0); };
       // the flags of the eight neighbours (and their psi, phi)
@@ -877,13 +1001,14 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
         nq[a] = L.pq[slot(ey(a))][lane + 1 + ex(a)];
         nt[a] = flags_of<T>(nq[a].fl);
       }
+      const bool liq = colin && is_liq(nt[0]);  // liquid mark of this step (Sec. 4.5)
       // The amendments of Sec. 4.5 move content between lattice nodes only:
       // beyond the free outlet there is no node to give, take or be counted,
       // so their neighbour flags (am) see a wall there; transport and forces
       // (nt) see the ghost row.
       const bool top_out = outy && R == ny - 1;
       auto am = [&](int a) -> uint32_t { return (top_out && ey(a) > 0) ? (uint32_t)TB_WALL : nt[a]; };
-      // node flags two links away (rare amendment paths)
+      // node flags two links away (the rare stranded-population path)
       auto far_flags = [&](int dx, int dy) -> uint32_t {
         if (outy && R + dy >= ny) return TB_WALL;
         const uint32_t v = word_at(X + dx, R + dy);
@@ -893,6 +1018,48 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
       const T ps = nq[0].ps, q1 = nq[0].q1, q2 = nq[0].q2;
       T(&f)[2][9] = fc;
       T(&g)[NSA][5] = gc;
+
+      // Solute amendments (Sec. 4.5; Step 2): the shares in transit from D2Q5
+      // neighbours that left the liquid set last step reach this node if it
+      // was liquid then; a node that turns liquid without content starts at
+      // zero (a node that was sending shares has handed its content over).
+      T Cin[NSA];
+#pragma unroll
+      for (int kk = 0; kk < NSA; ++kk) Cin[kk] = T(0);
+      if (NS > 0) {
+        bool any_in = false;
+#pragma unroll
+        for (int a = 1; a < 5; ++a) any_in |= !(am(a) & TB_WALL) && sf_of(am(a)) == SF_SHARE;
+        any_in = any_in && sf == SF_STREAM;
+        if (any_in) {
+#pragma unroll
+          for (int a = 1; a < 5; ++a)
+            if (!(am(a) & TB_WALL) && sf_of(am(a)) == SF_SHARE) {
+              const int sl = slot(ey(a)), lx = lane + 1 + ex(a);
+#pragma unroll
+              for (int kk = 0; kk < NS; ++kk) Cin[kk] += L.C[kk][sl][lx];
+            }
+        }
+        if (liq && (sf == SF_NONE || sf == SF_SHARE)) {
+#pragma unroll
+          for (int kk = 0; kk < NSA; ++kk) {
+            m.C[kk] = T(0);
+#pragma unroll
+            for (int a = 0; a < 5; ++a) g[kk][a] = T(0);
+          }
+        }
+      }
+      // concentration of a liquid D2Q5 neighbour as its own collision sees it
+      auto nbr_C = [&](int a, int kk) -> T {
+        const uint32_t v = nt[a];
+        const int nsf = sf_of(v);
+        if (nsf == SF_NONE || nsf == SF_SHARE) return T(0);  // liquid without content
+        T cn = T(0);
+#pragma unroll
+        for (int q = 0; q < NS; ++q)
+          if (q == kk) cn = L.C[q][slot(ey(a))][lane + 1 + ex(a)];
+        return cn;
+      };
 
       bool precip = false;
       bool storef = false, storeg = false;  // this lane holds valid post-collision populations
@@ -907,21 +1074,36 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
         // (their mean when both are fluid), else the centre.  The ring holds
         // zero psi / phi at non-fluid nodes, so an axis link's share is the
         // centre's value times the axis solid-neighbour sum.
+        // In FP32 the sums take each neighbour's difference from the centre
+        // value (the weighted link vectors sum to zero, so this is the same
+        // sum): in a smooth region the differences are small and exact, and
+        // the sum keeps its accuracy instead of cancelling large terms.
         T c1x = 0, c1y = 0, c12x = 0, c12y = 0, c21x = 0, c21y = 0, swx = 0, swy = 0, sax = 0, say = 0;
+        const T ps0 = SFORM ? ps : T(0), q10 = SFORM ? q1 : T(0), q20 = SFORM ? q2 : T(0);
 #pragma unroll
         for (int a = 1; a < 9; ++a) {
           const bool nf = !is_fluid(nt[a]);
           const T sw = nf ? T(1) : T(0);
-          T vps = nq[a].ps, vq1 = nq[a].q1, vq2 = nq[a].q2;
+          T vps = nq[a].ps - ps0, vq1 = nq[a].q1 - q10, vq2 = nq[a].q2 - q20;
+          if (SFORM && nf && a < 5) vps = vq1 = vq2 = T(0);  // the centre's mirror image
           if (a >= 5) {
             const int ax = ex(a) > 0 ? 1 : 3, ay = ey(a) > 0 ? 2 : 4;
             const bool fx = is_fluid(nt[ax]), fy = is_fluid(nt[ay]);
             const T h = (fx && fy) ? T(0.5) : T(1);
-            const bool own = !fx && !fy;
+            const bool ownm = !fx && !fy;
             if (nf) {
-              vps = own ? ps : (nq[ax].ps + nq[ay].ps) * h;
-              vq1 = own ? q1 : (nq[ax].q1 + nq[ay].q1) * h;
-              vq2 = own ? q2 : (nq[ax].q2 + nq[ay].q2) * h;
+              if constexpr (SFORM) {
+                const T dxp = fx ? nq[ax].ps - ps : T(0), dyp = fy ? nq[ay].ps - ps : T(0);
+                const T dx1 = fx ? nq[ax].q1 - q1 : T(0), dy1 = fy ? nq[ay].q1 - q1 : T(0);
+                const T dx2 = fx ? nq[ax].q2 - q2 : T(0), dy2 = fy ? nq[ay].q2 - q2 : T(0);
+                vps = (dxp + dyp) * h;
+                vq1 = (dx1 + dy1) * h;
+                vq2 = (dx2 + dy2) * h;
+              } else {
+                vps = ownm ? ps : (nq[ax].ps + nq[ay].ps) * h;
+                vq1 = ownm ? q1 : (nq[ax].q1 + nq[ay].q1) * h;
+                vq2 = ownm ? q2 : (nq[ax].q2 + nq[ay].q2) * h;
+              }
             }
           }
           if (ex(a) != 0) {
@@ -939,12 +1121,14 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
             if (a < 5) say += T(wf(a) * ey(a)) * sw;
           }
         }
-        c1x += ps * sax;
-        c1y += ps * say;
-        c12x += q2 * sax;
-        c12y += q2 * say;
-        c21x += q1 * sax;
-        c21y += q1 * say;
+        if constexpr (!SFORM) {
+          c1x += ps * sax;
+          c1y += ps * say;
+          c12x += q2 * sax;
+          c12y += q2 * say;
+          c21x += q1 * sax;
+          c21y += q1 * say;
+        }
         const T r1 = m.rho[0], r2 = m.rho[1];
         T Fx[2], Fy[2];
         Fx[0] = -k.G11 * ps * c1x - k.G12 * q1 * c12x - k.w1 * ps * swx + r1 * k.gx;
@@ -979,7 +1163,7 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
           T Sk[NSA];
 #pragma unroll
           for (int kk = 0; kk < NSA; ++kk) Sk[kk] = T(0);
-          T Ss[2] = {T(0), T(0)};
+          T Sg = T(0);  // gas component's source; the liquid component's is -Sg
           if (liq) {
             // solid types among the D2Q5 neighbours (surface-enhanced rates)
             uint32_t nbt = 0u;
@@ -1002,17 +1186,16 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
                 if (cg < T(0)) cg = T(0);
                 Rr = kr * (sel<NS>(m.C, c.hre0[r]) -
                            cdiv<T>(sel<NS>(m.C, c.hpr0[r]) * dsqrt<T>(cg), k.hKeq[r], k.r_hKeq[r]));
-                Ss[0] -= T(0.5) * Rr * k.hMgas[r];
-                Ss[1] += T(0.5) * Rr * k.hMgas[r];
+                Sg += T(0.5) * Rr * k.hMgas[r];
               }
 #pragma unroll
               for (int kk = 0; kk < NS; ++kk) Sk[kk] += k.hnu[r][kk] * Rr;
             }
-            l_msrc[0] += Ss[0];
-            l_msrc[1] += Ss[1];
+            l_msrc += (double)Sg;
 #pragma unroll
-            for (int kk = 0; kk < NS; ++kk) l_ssrc[kk] += Sk[kk];
+            for (int kk = 0; kk < NS; ++kk) l_ssrc[kk] += (double)Sk[kk];
           }
+          const T Ss[2] = {T(0) - Sg, Sg};
           // flow collision (Eq. 6, 8)
 #pragma unroll
           for (int s = 0; s < 2; ++s) {
@@ -1025,6 +1208,17 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
                 const T eu = (ex(a) == 0 ? T(0) : T(ex(a)) * ux[s]) + (ey(a) == 0 ? T(0) : T(ey(a)) * uy[s]);
                 const T feq = T(w9(a)) * m.rho[s] * (T(1) + T(3) * eu + T(4.5) * eu * eu - T(1.5) * usq);
                 f[s][a] = f[s][a] - om * (f[s][a] - feq) + T(w9(a)) * Ss[s];
+              }
+            } else if constexpr (SFORM) {
+              // Eq. 6 and 8 divided by w_a, on the deviations from the decoding
+              // reference R: s* = (1-om) s + om (rho - R + rho P_a) + S, with
+              // P_a = 3 e.u + 4.5 (e.u)^2 - 1.5 u^2
+              const T oneom = T(1) - om;
+#pragma unroll
+              for (int a = 0; a < 9; ++a) {
+                const T eu = (ex(a) == 0 ? T(0) : T(ex(a)) * ux[s]) + (ey(a) == 0 ? T(0) : T(ey(a)) * uy[s]);
+                const T P = eu * (T(3) + T(4.5) * eu) - T(1.5) * usq;
+                f[s][a] = oneom * f[s][a] + om * (m.drho[s] + m.rho[s] * P) + Ss[s];
               }
             } else {
               // the same update factored: f* = (1-om) f + om w rho (1 - 1.5 u^2 + eu (3 + 4.5 eu)) + w S
@@ -1060,7 +1254,7 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
             for (int s = 0; s < 2; ++s)
               if (don[s] != T(0)) {
 #pragma unroll
-                for (int a = 0; a < 9; ++a) f[s][a] += T(w9(a)) * don[s];
+                for (int a = 0; a < 9; ++a) f[s][a] += SFORM ? don[s] : T(w9(a)) * don[s];
               }
           }
           storef = true;
@@ -1079,6 +1273,17 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
                   const T geq = m.C[kk] * (J + T(0.5) * eu);
                   g[kk][a] = g[kk][a] - om * (g[kk][a] - geq) + J * Sk[kk];
                 }
+              } else if constexpr (SFORM) {
+                // Eq. 20-21 divided by J'_a: t* = (1-om) t + om C + S + (om C / (2 J'_a)) e.u
+                const T oneom = T(1) - om;
+                const T b = om * m.C[kk] + Sk[kk];
+                const T hc = om * m.C[kk] * k.hJ[kk];
+                const T hx = hc * urx, hy = hc * ury;
+                g[kk][0] = oneom * g[kk][0] + b;
+                g[kk][1] = oneom * g[kk][1] + b + hx;
+                g[kk][2] = oneom * g[kk][2] + b + hy;
+                g[kk][3] = oneom * g[kk][3] + b - hx;
+                g[kk][4] = oneom * g[kk][4] + b - hy;
               } else {
                 // factored: g* = (1-om) g + J (om C + S) + (om C / 2) e.u
                 const T oneom = T(1) - om;
@@ -1093,30 +1298,14 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
                 g[kk][4] = oneom * g[kk][4] + b1 - hy;
               }
             }
-            // (b) solute of a node that left the liquid set goes, at rest, equally
-            // to its liquid D2Q5 neighbours
-            bool any_don = false;
-#pragma unroll
-            for (int a = 1; a < 5; ++a) any_don |= !(nt[a] & TB_WALL) && (nt[a] & TB_LIQP) && !(nt[a] & LF_LIQN);
-            if (any_don) {
-              T donk[NSA];
-#pragma unroll
-              for (int kk = 0; kk < NSA; ++kk) donk[kk] = T(0);
-#pragma unroll
-              for (int a = 1; a < 5; ++a) {
-                if (!(am(a) & TB_WALL) && (am(a) & TB_LIQP) && !(am(a) & LF_LIQN)) {
-                  int mm = 0;
-#pragma unroll 1
-                  for (int b = 1; b < 5; ++b) mm += is_liq(far_flags(ex(a) + ex(b), ey(a) + ey(b))) ? 1 : 0;
-                  const int sl = slot(ey(a)), lx = lane + 1 + ex(a);
-#pragma unroll
-                  for (int kk = 0; kk < NS; ++kk) donk[kk] += L.C[kk][sl][lx] / T(mm);
-                }
-              }
+            // (b) the shares taken this step, at rest
+            if (sf == SF_STREAM) {
 #pragma unroll
               for (int kk = 0; kk < NS; ++kk)
+                if (Cin[kk] != T(0)) {
 #pragma unroll
-                for (int a = 0; a < 5; ++a) g[kk][a] += k.J[kk][a] * donk[kk];
+                  for (int a = 0; a < 5; ++a) g[kk][a] += SFORM ? Cin[kk] : k.J[kk][a] * Cin[kk];
+                }
             }
             // heterogeneous link fluxes (Eq. 29-31, A2): a population heading into a
             // reactive solid comes back next step minus the reactant's (plus the
@@ -1151,12 +1340,12 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
                   for (int r = 0; r < c.nhet; ++r) {
                     if (!(c.xsurf[r] & (1 << tj))) continue;
                     if (c.xre[r] == kk) {
-                      g[kk][a] -= phi[r];
-                      l_shet[kk] -= phi[r];
+                      g[kk][a] -= SFORM ? phi[r] * k.iJ1[kk] : phi[r];
+                      l_shet[kk] -= (double)phi[r];
                     }
                     if (c.xpr[r] == kk) {
-                      g[kk][a] += phi[r];
-                      l_shet[kk] += phi[r];
+                      g[kk][a] += SFORM ? phi[r] * k.iJ1[kk] : phi[r];
+                      l_shet[kk] += (double)phi[r];
                     }
                   }
                 }
@@ -1182,12 +1371,12 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
       uint32_t wout = 0;
       bool dissolved = false;
       T rdis[2] = {T(0), T(0)};  // density given to a dissolved node
+      bool r_diss = false, r_strand = false, r_l2g = false, r_g2l = false, r_pre = false;
+      double r_v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // mass_inj 1, 2, mass_rem 1, 2, vol_clip
       if (!EXPORT && own) {
         uint32_t tnew = (uint32_t)t;
-        bool lnew = false;
         if (t == T_FLUID) {
           if (precip) tnew = T_F;
-          else lnew = (double)m.rho[0] > thr;
         } else if (t == T_D || t == T_F) {
           // volume of pixel at a reactive solid node (Eq. 33; A2): sum of the
           // fluxes on its D2Q5 links to liquid nodes, in direction then reaction order
@@ -1197,16 +1386,11 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
 #pragma unroll
             for (int a = 1; a < 5; ++a) {
               if (!is_liq(nt[a])) continue;
-              const int sl = slot(ey(a)), lx = lane + 1 + ex(a);
               for (int r = 0; r < c.nhet; ++r) {
                 if (!(c.xsurf[r] & (1 << t))) continue;
                 const int md = c.xmode[r];
                 if (md != HET_CONSUMES && md != HET_MINERAL) continue;
-                T cn = T(0);
-#pragma unroll
-                for (int kk = 0; kk < NS; ++kk)
-                  if (kk == c.xre[r]) cn = L.C[kk][sl][lx];
-                T v = k.xkap[r] * (cn - k.xCeq[r]);
+                T v = k.xkap[r] * (nbr_C(a, c.xre[r]) - k.xCeq[r]);
                 if (c.xirrev[r] && v < T(0)) v = T(0);
                 if (md == HET_CONSUMES) dv -= c.xmvol[r] * (double)v;
                 else dv += c.xmvol[r] * (double)v;
@@ -1233,27 +1417,26 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
             }
             if (nf > 0) {
               // (c) dissolved: fluid from the next step, at rest with the mean
-              // density of its fluid neighbours and no solute.  Its next status
-              // word names no fluid neighbour, so the next pull reads its own
-              // slots back (slot opp(a) for direction a: the rest populations
-              // are the same in opposite directions).
+              // density of its fluid neighbours.  Its next status word names
+              // no fluid neighbour, so the next pull reads its own slots back
+              // (slot opp(a) for direction a: the rest populations are the
+              // same in opposite directions).
               const T rb0 = sum0 / T(nf), rb1 = sum1 / T(nf);
               rdis[0] = rb0;
               rdis[1] = rb1;
 #pragma unroll
               for (int a = 0; a < 9; ++a) {
-                f[0][a] = T(w9(a)) * rb0;
-                f[1][a] = T(w9(a)) * rb1;
+                f[0][a] = SFORM ? rb0 : T(w9(a)) * rb0;
+                f[1][a] = SFORM ? rb1 : T(w9(a)) * rb1;
               }
               storef = true;
               dissolved = true;
-              atomicAdd(&L.rare[0], (double)rb0);
-              atomicAdd(&L.rare[1], (double)rb1);
-              atomicAdd(&L.rare[4], Vn);
-              atomicAdd(&L.rare[6], 1.0);
+              r_diss = true;
+              r_v[0] = (double)rb0;
+              r_v[1] = (double)rb1;
+              r_v[4] = Vn;
               A.V[idx] = 0.0;
               tnew = T_FLUID;
-              lnew = (double)rb0 > thr;
             }
           }
           if (w & TB_STR) {
@@ -1261,29 +1444,44 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
 #pragma unroll
             for (int b = 1; b < 9; ++b) mm += is_fluid(am(b)) ? 1 : 0;
             if (mm == 0) {
-              atomicAdd(&L.rare[2], (double)m.rho[0]);
-              atomicAdd(&L.rare[3], (double)m.rho[1]);
+              r_strand = true;
+              r_v[2] = (double)m.rho[0];
+              r_v[3] = (double)m.rho[1];
             }
           }
         }
-        // a node leaving the liquid set with no liquid neighbour to take its solute
-        if (liqp && !liq) {
+        // (b) a node that holds solute but is not liquid now passes its content
+        // (and the shares it took) in equal shares, at rest, to its D2Q5
+        // neighbours that are liquid now, which take them next step; with no
+        // such neighbour it keeps the content at rest in its own slots
+        int sfn = liq ? SF_STREAM : SF_NONE;
+        if (NS > 0 && !liq && (sf == SF_STREAM || sf == SF_HOLD)) {
           int mm = 0;
 #pragma unroll
           for (int b = 1; b < 5; ++b) mm += is_liq(am(b)) ? 1 : 0;
-          if (mm == 0) {
+          bool any = false;
 #pragma unroll
-            for (int kk = 0; kk < NS; ++kk) atomicAdd(&L.rare[8 + kk], (double)m.C[kk]);
+          for (int kk = 0; kk < NS; ++kk) {
+            T cv = m.C[kk];
+            if (sf == SF_STREAM) cv += Cin[kk];
+            if (mm > 0) cv = cv / T(mm);
+            any |= cv != T(0);
+#pragma unroll
+            for (int a = 0; a < 5; ++a) g[kk][a] = SFORM ? cv : k.J[kk][a] * cv;
           }
-          if (t == T_FLUID) atomicAdd(&L.rare[16], 1.0);
+          if (any) {
+            sfn = mm > 0 ? SF_SHARE : SF_HOLD;
+            storeg = true;
+          }
         }
-        if (liq && !liqp) atomicAdd(&L.rare[17], 1.0);
+        r_l2g = sf == SF_STREAM && !liq && t == T_FLUID;
+        r_g2l = liq && sf != SF_STREAM;
         const bool to_f = (t == T_FLUID && tnew == T_F);
-        if (to_f) atomicAdd(&L.rare[7], 1.0);
-        // status word of the next step: type, liquid marks, stranded flag, and
+        r_pre = to_f;
+        // status word of the next step: type, solute state, stranded flag, and
         // which neighbours are fluid / liquid now (the next pull follows them)
-        wout = tnew | (lnew ? TB_LIQ : 0u) | (liq ? TB_LIQP : 0u) | (to_f ? TB_STR : 0u);
-        if constexpr (DEV) {
+        wout = tnew | ((uint32_t)sfn << SF_SHIFT) | (to_f ? TB_STR : 0u);
+        if constexpr (REFS) {
           // reference codes of the populations stored now (the node's own
           // density, or the one a dissolved node is given)
           const T d0 = dissolved ? rdis[0] : m.rho[0], d1 = dissolved ? rdis[1] : m.rho[1];
@@ -1292,8 +1490,36 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
         if (!dissolved) {
 #pragma unroll
           for (int b = 1; b < 9; ++b) wout |= (nt[b] & LF_FLU) << (NBF_SHIFT + b - 1 - 6);
+          if (liq) {
 #pragma unroll
-          for (int b = 1; b < 5; ++b) wout |= (nt[b] & LF_LIQN) << (NBL_SHIFT + b - 1 - 5);
+            for (int b = 1; b < 5; ++b) wout |= (nt[b] & LF_LIQN) << (NBL_SHIFT + b - 1 - 5);
+          }
+        }
+      }
+      if (!EXPORT) {
+        // the rare balances of this row: wave sums in a fixed order, added by lane 0
+        const unsigned long long bd = __ballot(r_diss), bs = __ballot(r_strand);
+        const unsigned long long bl = __ballot(r_l2g), bgl = __ballot(r_g2l), bp = __ballot(r_pre);
+        if (bd) {
+          const double s0_ = wave_sum_det(r_v[0]), s1_ = wave_sum_det(r_v[1]), s4_ = wave_sum_det(r_v[4]);
+          if (lane == 0) {
+            L.rare[0] += s0_;
+            L.rare[1] += s1_;
+            L.rare[4] += s4_;
+            L.rare[6] += (double)__popcll(bd);
+          }
+        }
+        if (bs) {
+          const double s2_ = wave_sum_det(r_v[2]), s3_ = wave_sum_det(r_v[3]);
+          if (lane == 0) {
+            L.rare[2] += s2_;
+            L.rare[3] += s3_;
+          }
+        }
+        if (lane == 0) {
+          if (bp) L.rare[7] += (double)__popcll(bp);
+          if (bl) L.rare[8] += (double)__popcll(bl);
+          if (bgl) L.rare[9] += (double)__popcll(bgl);
         }
       }
 
@@ -1305,8 +1531,13 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
             A.o_ux[idx] = 0.0;
             A.o_uy[idx] = 0.0;
           }
+          // the solute each node holds once the shares in transit are delivered
 #pragma unroll
-          for (int kk = 0; kk < NS; ++kk) A.o_C[(size_t)kk * c.plane + idx] = (double)m.C[kk];
+          for (int kk = 0; kk < NS; ++kk) {
+            const T cv = sf == SF_STREAM ? m.C[kk] + Cin[kk] : (sf == SF_HOLD ? m.C[kk] : T(0));
+            A.o_C[(size_t)kk * c.plane + idx] = (double)cv;
+          }
+          A.o_L[idx] = liq ? 1.0 : 0.0;
         }
       } else {
         // -------------------------------------------------- own-slot stores
@@ -1335,7 +1566,7 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
         const unsigned xo = (unsigned)X * PE;
         if (gf) {
           const unsigned vo = xo + (unsigned)R * RSF;
-          if constexpr (DEV) {
+          if constexpr (REFS) {
             // deviation from w_a x the reference of the node that pulls the
             // population next step: the neighbour it heads to if that one is
             // fluid now, else this node (bounce-back; a dissolved node reads
@@ -1347,13 +1578,30 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
             } else {
               ro = L.rf[s0][lane + 1];
             }
+            if constexpr (DEV) {
 #pragma unroll
-            for (int a = 0; a < 9; ++a) {
-              RF<T> rd = ro;
-              if (a != 0 && !dissolved && is_fluid(nt[a])) rd = L.rf[slot(ey(a))][lane + 1 + ex(a)];
-              bstore2<ST>(dev_out<SM>(__builtin_fmaf(f[0][a], k.sc[0], -(k.wsc[0][wcls(a)] * rd.r1))),
-                          dev_out<SM>(__builtin_fmaf(f[1][a], k.sc[1], -(k.wsc[1][wcls(a)] * rd.r2))), wf_, vo,
-                          (unsigned)a * PS);
+              for (int a = 0; a < 9; ++a) {
+                RF<T> rd = ro;
+                if (a != 0 && !dissolved && is_fluid(nt[a])) rd = L.rf[slot(ey(a))][lane + 1 + ex(a)];
+                bstore2<ST>(dev_out<SM>(__builtin_fmaf(f[0][a], k.sc[0], -(k.wsc[0][wcls(a)] * rd.r1))),
+                            dev_out<SM>(__builtin_fmaf(f[1][a], k.sc[1], -(k.wsc[1][wcls(a)] * rd.r2))), wf_, vo,
+                            (unsigned)a * PS);
+              }
+            } else {
+              // FP32: s_a is a deviation from the decoding reference of this
+              // step (zero for a dissolved node, which holds rest populations
+              // w_a rho); re-referenced to the reader's, an exact difference of
+              // two coded values.  The top row's downward populations at a free
+              // outlet keep reference zero (they have two readers).
+              T o1 = T(0), o2 = T(0);
+              if (!dissolved) refs_of(w, o1, o2);
+#pragma unroll
+              for (int a = 0; a < 9; ++a) {
+                RF<T> rd = ro;
+                if (a != 0 && !dissolved && is_fluid(nt[a])) rd = L.rf[slot(ey(a))][lane + 1 + ex(a)];
+                if (top_out && ey(a) < 0) rd = RF<T>{T(0), T(0)};
+                bstore2<ST>(f[0][a] + (o1 - rd.r1), f[1][a] + (o2 - rd.r2), wf_, vo, (unsigned)a * PS);
+              }
             }
           } else {
 #pragma unroll
@@ -1368,9 +1616,10 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
             T co_[NSA];
 #pragma unroll
             for (int kk = 0; kk < NSA; ++kk) co_[kk] = L.Cf[kk][s0][lane + 1];
+            const bool donor = !liq;  // a node sending shares or keeping content reads its own slots
 #pragma unroll
             for (int a = 0; a < 5; ++a) {
-              const bool nbr = a != 0 && is_liq(nt[a]);
+              const bool nbr = a != 0 && !donor && is_liq(nt[a]);
 #pragma unroll
               for (int j = 0; j < NGR; ++j) {
                 Grp<ST, SG> hv;
@@ -1437,18 +1686,17 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
   if (EXPORT) return;
 
   // ---------------------------------------------------------- item balances
-  // Wave sums in the working precision (a wave whose values are all zero skips
-  // the shuffles), added to this item's FP64 record (the item is this
-  // wavefront's alone, so plain read-modify-write).
+  // Wave sums in FP64 in a fixed order (lane 0's butterfly), added to this
+  // item's FP64 record (the item is this wavefront's alone, so plain
+  // read-modify-write).
   const T wm = wave_max_t(my_rmax);
-  const T v0 = wave_sum_t(l_msrc[0]);
-  const T v1 = wave_sum_t(l_msrc[1]);
-  const double vd = wave_sum_t(l_vdv);
-  T vs[NSA], vh[NSA];
+  const double vg = __ballot(l_msrc != 0.0) ? wave_sum_det(l_msrc) : 0.0;
+  const double vd = __ballot(l_vdv != 0.0) ? wave_sum_det(l_vdv) : 0.0;
+  double vs[NSA], vh[NSA];
 #pragma unroll
   for (int kk = 0; kk < NSA; ++kk) {
-    vs[kk] = wave_sum_t(l_ssrc[kk]);
-    vh[kk] = wave_sum_t(l_shet[kk]);
+    vs[kk] = __ballot(l_ssrc[kk] != 0.0) ? wave_sum_det(l_ssrc[kk]) : 0.0;
+    vh[kk] = __ballot(l_shet[kk] != 0.0) ? wave_sum_det(l_shet[kk]) : 0.0;
   }
   double* Lg = A.led + (size_t)item * NLED;
   if (lane == 0) {
@@ -1461,13 +1709,15 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
     if (md > 0.0 && mb > seen) atomicMax(part, mb);
     if (item == 0)
       for (int xc = 0; xc < 8; ++xc) A.rmax[slot_next * RM_SLOT + xc * RM_STRIDE] = 0ull;
-    if (v0 != T(0)) Lg[L_MSRC] += (double)v0;
-    if (v1 != T(0)) Lg[L_MSRC + 1] += (double)v1;
+    if (vg != 0.0) {
+      Lg[L_MSRC] += -vg;
+      Lg[L_MSRC + 1] += vg;
+    }
     if (vd != 0.0) Lg[L_VDV] += vd;
 #pragma unroll
     for (int kk = 0; kk < NS; ++kk) {
-      if (vs[kk] != T(0)) Lg[L_SSRC + kk] += (double)vs[kk];
-      if (vh[kk] != T(0)) Lg[L_SHET + kk] += (double)vh[kk];
+      if (vs[kk] != 0.0) Lg[L_SSRC + kk] += vs[kk];
+      if (vh[kk] != 0.0) Lg[L_SHET + kk] += vh[kk];
     }
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -1548,7 +1798,7 @@ struct lbrx_ctx {
   double* led = nullptr;
   double* ledsum = nullptr;
   unsigned int* err = nullptr;
-  double* out = nullptr;  // export scratch: (4 + ns) planes
+  double* out = nullptr;  // export scratch: (5 + ns) planes
   void* dargs = nullptr;  // this simulation's KArgs in device memory
   int cur = 0;
   int64_t steps = 0;
@@ -1705,9 +1955,39 @@ void fill_populations(const lbrx_params* p, const KConst& c, const std::vector<u
         f[fslot(c, y, a, x, 0)] = T(w9(a) * p->rho1[i]);
         f[fslot(c, y, a, x, 1)] = T(w9(a) * p->rho2[i]);
       }
-      if (tb[d] & TB_LIQ)
+      if (sf_of(tb[d]) == SF_STREAM)
         for (int k = 0; k < ns; ++k)
           for (int a = 0; a < 5; ++a) g[gslot(c, y, k, a, x)] = T(c.J[k][a] * p->C0[(long long)k * nx * ny + i]);
+    }
+}
+
+// FP32 storage: the rest equilibria of Eq. 8 and 21 as the kernels keep them.
+// A flow slot holds f_a / w_a - R = rho - R, R the reference density coded in
+// the node's status word (every node reads its own slots at step 0); at a
+// free outlet the top row's downward slots keep reference zero (they have two
+// readers).  A solute slot holds g_a / J'_a = C.
+void fill_sform_populations(const lbrx_params* p, const KConst& c, const KT<float>& k, std::vector<uint32_t>& tb,
+                            std::vector<float>& f, std::vector<float>& g) {
+  const int nx = p->nx, ny = p->ny, ns = p->n_species;
+  const bool outlet = c.per_y == 2;
+  f.assign(f_elems(c), 0.0f);
+  g.assign(g_elems(c), 0.0f);
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      const long long i = (long long)y * nx + x, d = (long long)y * c.pitch + x;
+      if ((tb[d] & TB_T) != T_FLUID) continue;
+      const double r[2] = {p->rho1[i], p->rho2[i]};
+      const uint32_t c1 = ref_code((float)r[0], k.rb1, SH1, MAX1), c2 = ref_code((float)r[1], k.rb2, SH2, MAX2);
+      tb[d] |= put_codes(c1, c2);
+      const double ref[2] = {(double)ref_value(c1, k.rb1, SH1), (double)ref_value(c2, k.rb2, SH2)};
+      for (int s = 0; s < 2; ++s)
+        for (int a = 0; a < 9; ++a) {
+          const bool zref = outlet && y == ny - 1 && ey(a) < 0;
+          f[fslot(c, y, a, x, s)] = (float)(zref ? r[s] : r[s] - ref[s]);
+        }
+      if (sf_of(tb[d]) == SF_STREAM)
+        for (int q = 0; q < ns; ++q)
+          for (int a = 0; a < 5; ++a) g[gslot(c, y, q, a, x)] = (float)p->C0[(long long)q * nx * ny + i];
     }
 }
 
@@ -1725,6 +2005,23 @@ double pow2_scale(double vmax) {
 uint32_t code_base(double v, int sh) {
   const float f = (float)(v > 1e-30 ? v : 1e-30);
   return __builtin_bit_cast(uint32_t, f) >> sh;
+}
+
+// Bases of the flow reference codes (FP32 and 16-bit storage): sixteen
+// binades upward from an eighth of the smallest initial density.
+void fill_ref_bases(KT<float>& k, const lbrx_params* p) {
+  const long long N = (long long)p->nx * p->ny;
+  double mx[2] = {0.0, 0.0}, mn[2] = {1e300, 1e300};
+  for (long long i = 0; i < N; ++i) {
+    if (p->node_type[i] != LBRX_FLUID) continue;
+    const double r[2] = {p->rho1[i], p->rho2[i]};
+    for (int s = 0; s < 2; ++s) {
+      mx[s] = std::max(mx[s], r[s]);
+      if (r[s] > 0.0) mn[s] = std::min(mn[s], r[s]);
+    }
+  }
+  k.rb1 = code_base((mn[0] < 1e300 ? mn[0] : 1.0) / 8.0, SH1);
+  k.rb2 = code_base(std::max(mn[1] < 1e300 ? mn[1] : 0.0, 1e-3 * mx[1]) / 8.0, SH2);
 }
 
 void fill_dev_constants(KT<float>& k, const lbrx_params* p, const KConst& c) {
@@ -1753,8 +2050,6 @@ void fill_dev_constants(KT<float>& k, const lbrx_params* p, const KConst& c) {
     for (int q = 0; q < 3; ++q) k.wsc[s][q] = (float)(wv[q] * sc);
   }
   for (int q = 0; q < 3; ++q) k.wc[q] = (float)wv[q];
-  k.rb1 = code_base((mn[0] < 1e300 ? mn[0] : 1.0) / 8.0, SH1);
-  k.rb2 = code_base(std::max(mn[1] < 1e300 ? mn[1] : 0.0, 1e-3 * mx[1]) / 8.0, SH2);
   const double scg = pow2_scale(csum);
   for (int q = 0; q < LBRX_MAX_SPECIES; ++q) {
     k.scg[q] = (float)scg;
@@ -1800,7 +2095,7 @@ void fill_dev_populations(const lbrx_params* p, const KConst& c, const KT<float>
           const float f0 = (float)(w9(a) * (s == 0 ? p->rho1[i] : p->rho2[i]));
           f[fslot(c, y, a, x, s)] = dev_store_host(std::fma(f0, k.sc[s], -(k.wsc[s][wcls(a)] * ref[s])), sm);
         }
-      if ((tb[d] & TB_LIQ) && ns > 0) {
+      if (sf_of(tb[d]) == SF_STREAM && ns > 0) {
         for (int q = 0; q < ns; ++q) {
           const float C = (float)p->C0[(long long)q * nx * ny + i];
           const uint32_t cc = ref_code(C, k.rbc[q], SHC, MAXC);
@@ -1835,6 +2130,7 @@ void make_args(const lbrx_ctx* x, KArgs<T>& A, const KT<T>& kt) {
   A.o_ux = x->out ? x->out + 2 * plane : nullptr;
   A.o_uy = x->out ? x->out + 3 * plane : nullptr;
   A.o_C = x->out ? x->out + 4 * plane : nullptr;
+  A.o_L = x->out ? x->out + (4 + (size_t)x->c.ns) * plane : nullptr;
 }
 
 // (re)writes the simulation's device-resident KArgs (synchronous copy)
@@ -1898,6 +2194,13 @@ void fill_kt(KT<T>& k, const lbrx_params* p, const KConst& c, const double* D) {
   for (int q = 0; q < LBRX_MAX_SPECIES; ++q) {
     k.omg[q] = (T)c.omg[q];
     for (int a = 0; a < 5; ++a) k.J[q][a] = (T)c.J[q][a];
+    // J1' = J1 rounded to a multiple of 2^-26, J0' = 1 - 4 J1' (both exact in
+    // FP32, so that they sum to one); used by FP32 storage only
+    const double j1 = q < c.ns ? std::nearbyint(c.J[q][1] * 67108864.0) / 67108864.0 : 0.25;
+    k.Jp1[q] = (T)j1;
+    k.Jp0[q] = (T)(1.0 - 4.0 * j1);
+    k.hJ[q] = (T)(j1 > 0.0 ? 0.5 / j1 : 0.0);
+    k.iJ1[q] = (T)(j1 > 0.0 ? 1.0 / j1 : 0.0);
   }
   for (int r = 0; r < LBRX_MAX_RXN; ++r) {
     k.hk[r] = (T)c.hk[r];
@@ -1988,6 +2291,7 @@ lbrx_status lbrx_create(const lbrx_params* p, void* hip_stream, lbrx_ctx** out) 
   c.a = p->a;
   c.b = p->b;
   c.G11 = p->G11;
+  c.rG11 = p->G11 != 0.0 ? 1.0 / p->G11 : 0.0;
   c.psi_pre = p->psi_prefactor > 0.0 ? p->psi_prefactor : 2.0;
   c.G12 = p->G12;
   c.G21 = p->G21;
@@ -2039,6 +2343,7 @@ lbrx_status lbrx_create(const lbrx_params* p, void* hip_stream, lbrx_ctx** out) 
   }
   fill_kt(x->kd, p, c, D);
   fill_kt(x->kf, p, c, D);
+  fill_ref_bases(x->kf, p);
   if (sm_dev(sm)) fill_dev_constants(x->kf, p, c);
   const bool outlet = c.per_y == 2;  // free outlet: the SM_OUT kernels (plain storage only)
   x->step64 = outlet ? pick<double, SM_OUT, false>(c.ns) : pick<double, SM_PLAIN, false>(c.ns);
@@ -2090,7 +2395,7 @@ lbrx_status lbrx_create(const lbrx_params* p, void* hip_stream, lbrx_ctx** out) 
       uint32_t b = t;
       // step 0: no neighbour bits, so every node reads its own slots, which
       // hold f(0) (and g(0) at liquid nodes)
-      if (t == LBRX_FLUID && p->rho1[i] > thr0) b |= TB_LIQ | TB_LIQP;
+      if (t == LBRX_FLUID && p->rho1[i] > thr0) b |= (uint32_t)SF_STREAM << SF_SHIFT;
       tb[d] = b;
       V[d] = p->V0 ? p->V0[i] : ((t == LBRX_SOLID_D || t == LBRX_SOLID_F) ? 1.0 : 0.0);
     }
@@ -2102,7 +2407,7 @@ lbrx_status lbrx_create(const lbrx_params* p, void* hip_stream, lbrx_ctx** out) 
     if (e == hipSuccess) e = hipMemcpy(x->g[0], g.data(), gbytes, hipMemcpyHostToDevice);
   } else if (sm == SM_PLAIN) {
     std::vector<float> f, g;
-    fill_populations<float>(p, c, tb, f, g);
+    fill_sform_populations(p, c, x->kf, tb, f, g);
     e = hipMemcpy(x->f[0], f.data(), fbytes, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(x->g[0], g.data(), gbytes, hipMemcpyHostToDevice);
   } else {
@@ -2328,11 +2633,11 @@ lbrx_status lbrx_fields(lbrx_ctx* x, lbrx_fields_out* o) {
   const KConst& c = x->c;
   const size_t plane = (size_t)c.plane;
   if (!x->out) {
-    if (!ctx_alloc(x, (void**)&x->out, (4 + (size_t)c.ns) * plane * 8))
+    if (!ctx_alloc(x, (void**)&x->out, (5 + (size_t)c.ns) * plane * 8))
       return set_err(x, LBRX_E_NOMEM, "device allocation of the read-out planes failed");
     HIPCHK(x, upload_args(x));
   }
-  HIPCHK(x, hipMemsetAsync(x->out, 0, (4 + (size_t)c.ns) * plane * 8, x->stream));
+  HIPCHK(x, hipMemsetAsync(x->out, 0, (5 + (size_t)c.ns) * plane * 8, x->stream));
   launch_one(x, true);
   HIPCHK(x, hipGetLastError());
   hipLaunchKernelGGL(k_ledger_sum, dim3(NLED), dim3(LSUM_THREADS), 0, x->stream, x->led, c.nitems, x->ledsum);
@@ -2349,14 +2654,17 @@ lbrx_status lbrx_fields(lbrx_ctx* x, lbrx_fields_out* o) {
   if (o->C)
     for (int k = 0; k < c.ns; ++k) HIPCHK(x, get2d(o->C + (size_t)k * c.nx * c.ny, x->out + (4 + k) * plane));
   if (o->V) HIPCHK(x, get2d(o->V, x->V));
-  if (o->type || o->liquid) {
+  if (o->type) {
     std::vector<uint32_t> tb((size_t)c.nx * c.ny);
     HIPCHK(x, hipMemcpy2D(tb.data(), (size_t)c.nx * 4, x->t[x->cur], (size_t)c.pitch * 4, (size_t)c.nx * 4, c.ny,
                           hipMemcpyDeviceToHost));
-    for (size_t i = 0; i < tb.size(); ++i) {
-      if (o->type) o->type[i] = tb[i] & TB_T;
-      if (o->liquid) o->liquid[i] = (tb[i] & TB_LIQ) ? 1 : 0;
-    }
+    for (size_t i = 0; i < tb.size(); ++i) o->type[i] = tb[i] & TB_T;
+  }
+  if (o->liquid) {
+    // this step's liquid marks, decided by the read-out kernel as by the step
+    std::vector<double> lq((size_t)c.nx * c.ny);
+    HIPCHK(x, get2d(lq.data(), x->out + (4 + (size_t)c.ns) * plane));
+    for (size_t i = 0; i < lq.size(); ++i) o->liquid[i] = lq[i] != 0.0 ? 1 : 0;
   }
   if (o->ledger) {
     double l[NLED];

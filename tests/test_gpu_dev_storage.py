@@ -75,7 +75,8 @@ BOUNDS_100 = {"f16dev": {"rho": 1e-3, "u": 1e-2}, "bf16dev": {"rho": 5e-3, "u": 
 @pytest.mark.parametrize("precision", ["f16dev", "bf16dev"])
 def test_droplet_accuracy_100_steps(precision):
     """The moving droplet after 1, 10 and 100 steps: densities and velocities
-    within the stated bounds of the FP64 oracle, node masks identical, and the
+    within the stated bounds of the FP64 oracle, node masks identical unless
+    the oracle has a liquid mark within the density bound of its threshold, and the
     mass of each component equal to its ledger balance within the 16-bit
     rounding of the stored deviations."""
     p = W.config0()
@@ -87,10 +88,13 @@ def test_droplet_accuracy_100_steps(precision):
         g.step(n - done)
         done = n
         G, O = g.fields(), o.fields()
-        errs, masks, near = compare(G, O, p, 1.0)
-        print(f"[{precision} {n}] " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
-        assert masks
         b = BOUNDS_100[precision]
+        errs, masks, near = compare(G, O, p, b["rho"])
+        print(f"[{precision} {n}] " + " ".join(f"{k}={v:.2e}" for k, v in errs.items())
+              + f" masks={masks} near={near}", flush=True)
+        # a liquid mark may flip where the oracle's density lies within the
+        # storage error of the threshold
+        assert masks or near
         for k in ("rho1", "rho2"):
             assert errs[k] <= b["rho"], (k, errs[k])
         for k in ("ux", "uy"):
