@@ -27,6 +27,9 @@
  */
 #include "lbrx_oracle.h"
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -40,6 +43,16 @@
  *              the share of its content due to each D2Q5 neighbour that was
  *              liquid then, delivered during this step */
 enum { SF_NONE = 0, SF_STREAM = 1, SF_HOLD = 2, SF_SHARE = 3 };
+
+/* Loops whose iterations touch only their own node's results may run on
+ * several host threads (orc_set_threads; OpenMP builds).  Every balance sum
+ * stays in a serial loop in node order, so the results are bit for bit those
+ * of one thread. */
+#ifdef _OPENMP
+#define PAR_FOR _Pragma("omp parallel for num_threads(s->nthreads) schedule(static)")
+#else
+#define PAR_FOR
+#endif
 
 /* D2Q9 velocities (Eq. 7); D2Q5 uses directions 0..4 of the same table (Sec. 3.2). */
 static const int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
@@ -83,6 +96,11 @@ struct orc_sim {
   double *rbar;             /* [2][N] mean density put into dissolved nodes */
   double D[ORC_MAX_SPECIES];
   double kap[ORC_MAX_RXN];
+  uint8_t *bad, *clamp;     /* per-node flags of sub-steps 1-2, examined in node order */
+  double *dvv;              /* per-node volume increment of sub-step 9 */
+  uint8_t *dvt;             /*   and whether the node had a reactive link */
+  int nthreads;
+  double margin_liq, margin_vol;  /* smallest decision margins since the last read-out */
   char err[256];
 };
 
@@ -222,6 +240,12 @@ orc_sim* orc_create(const orc_params* p, const uint8_t* type0, const double* V0,
   s->Sk = xcalloc((size_t)ns * N + 1, sizeof(double));
   s->Phi = xcalloc((size_t)ORC_MAX_RXN * N, sizeof(double));
   s->rbar = xcalloc((size_t)2 * N, sizeof(double));
+  s->bad = xcalloc(N, 1);
+  s->clamp = xcalloc(N, 1);
+  s->dvv = xcalloc(N, sizeof(double));
+  s->dvt = xcalloc(N, 1);
+  s->nthreads = 1;
+  s->margin_liq = s->margin_vol = INFINITY;
 
   /* Eq. 24: D = (1 - J0)(tau_g - 1/2)/2 */
   for (int k = 0; k < ns; ++k) s->D[k] = 0.5 * (1.0 - p->J0[k]) * (p->tau_g[k] - 0.5);
@@ -267,6 +291,7 @@ orc_sim* orc_create(const orc_params* p, const uint8_t* type0, const double* V0,
 void orc_destroy(orc_sim* s) {
   if (!s) return;
   void* ptrs[] = {s->f, s->fs, s->fn, s->g, s->gs, s->gn, s->type, s->liq, s->sflag, s->Cin, s->snext,
+                  s->bad, s->clamp, s->dvv, s->dvt,
                   s->stranded, s->tnext, s->V, s->rho, s->jx, s->jy, s->C, s->psi1,
                   s->phi1, s->phi2, s->Fx, s->Fy, s->ueqx, s->ueqy, s->urx, s->ury,
                   s->Ss, s->Sk, s->Phi, s->rbar};
@@ -275,6 +300,12 @@ void orc_destroy(orc_sim* s) {
 }
 
 const char* orc_error(orc_sim* s) { return s->err; }
+void orc_set_threads(orc_sim* s, int n) { s->nthreads = n > 0 ? n : 1; }
+void orc_margins(orc_sim* s, double* liq, double* vol) {
+  if (liq) *liq = s->margin_liq;
+  if (vol) *vol = s->margin_vol;
+  s->margin_liq = s->margin_vol = INFINITY;
+}
 int64_t orc_step_count(orc_sim* s) { return s->step; }
 
 static double J_of(const orc_params* p, int k, int a) {
@@ -302,8 +333,10 @@ static int macros(orc_sim* s) {
    * turned solid at the end of the previous step (their streamed-in
    * populations are still there).  g is valid where the node holds solute
    * (SF_*); at an SF_SHARE node its moment is the share in transit. */
+  PAR_FOR
   for (int i = 0; i < N; ++i) {
     const int validf = s->type[i] == ORC_FLUID || s->stranded[i];
+    s->bad[i] = 0;
     for (int sg = 0; sg < 2; ++sg) {
       double r = 0.0, jx = 0.0, jy = 0.0;
       if (validf) {
@@ -320,11 +353,7 @@ static int macros(orc_sim* s) {
     }
     if (validf) {
       const double r1 = s->rho[i], r2 = s->rho[N + i];
-      if (!(r1 >= 0.0) || !(r2 >= 0.0) || (s->type[i] == ORC_FLUID && !(r1 + r2 > 0.0))) {
-        snprintf(s->err, sizeof s->err, "unstable: bad density at node (%d,%d) step %lld",
-                 i % nx, i / nx, (long long)s->step);
-        return -1;
-      }
+      if (!(r1 >= 0.0) || !(r2 >= 0.0) || (s->type[i] == ORC_FLUID && !(r1 + r2 > 0.0))) s->bad[i] = 1;
     }
     for (int k = 0; k < ns; ++k) {
       double c = 0.0;
@@ -333,6 +362,12 @@ static int macros(orc_sim* s) {
       s->C[k * N + i] = c;
     }
   }
+  for (int i = 0; i < N; ++i)
+    if (s->bad[i]) {
+      snprintf(s->err, sizeof s->err, "unstable: bad density at node (%d,%d) step %lld",
+               i % nx, i / nx, (long long)s->step);
+      return -1;
+    }
 
   /* 2. effective masses at fluid nodes.
    * psi_1: Eq. 13 with the prefactor that makes the stencil of Eq. 11
@@ -341,26 +376,35 @@ static int macros(orc_sim* s) {
    * The printed 6/G11 belongs to weights whose second moment is c_s^2 I; it is
    * selected by psi_pre = 6.  A negative argument is clamped to zero and counted.
    * phi_1(rho_2), phi_2(rho_1): Eq. 15 with the natural logarithm in rho_10. */
+  PAR_FOR
   for (int i = 0; i < N; ++i) {
     s->psi1[i] = s->phi1[i] = s->phi2[i] = 0.0;
+    s->bad[i] = s->clamp[i] = 0;
     if (s->type[i] != ORC_FLUID) continue;
     const double r1 = s->rho[i], r2 = s->rho[N + i];
     if (p->G11 != 0.0) {
       if (!(0.25 * p->b * r1 < 1.0)) {
-        snprintf(s->err, sizeof s->err, "unstable: b*rho/4 >= 1 at node (%d,%d) step %lld",
-                 i % nx, i / nx, (long long)s->step);
-        return -1;
+        s->bad[i] = 1;
+        continue;
       }
       const double pre = p->psi_pre;
       double arg = pre * (p_cs(p, r1) - r1 / 3.0) / p->G11;
       if (arg < 0.0) {
         arg = 0.0;
-        s->led.n_psi_clamp += 1.0;
+        s->clamp[i] = 1;
       }
       s->psi1[i] = sqrt(arg);
     }
     if (p->rho20 > 0.0) s->phi1[i] = 1.0 - exp(-r2 / p->rho20);
     if (p->rho10 > 0.0) s->phi2[i] = p->a0 - exp(-r1 / p->rho10);
+  }
+  for (int i = 0; i < N; ++i) {
+    if (s->bad[i]) {
+      snprintf(s->err, sizeof s->err, "unstable: b*rho/4 >= 1 at node (%d,%d) step %lld",
+               i % nx, i / nx, (long long)s->step);
+      return -1;
+    }
+    if (s->clamp[i]) s->led.n_psi_clamp += 1.0;
   }
 
   /* 4. forces at fluid nodes (Eq. 11, 14, 16, body force).
@@ -373,6 +417,7 @@ static int macros(orc_sim* s) {
    * are fluid), else the centre node.  At a flat wall the sums then see the
    * reflected field, so with w = 0 the wall is neutral and a droplet meets
    * it at 90 degrees, as App. A.1 (Fig. A2) reports. */
+  PAR_FOR
   for (int i = 0; i < N; ++i) {
     for (int sg = 0; sg < 2; ++sg) s->Fx[sg * N + i] = s->Fy[sg * N + i] = 0.0;
     if (s->type[i] != ORC_FLUID) continue;
@@ -433,6 +478,7 @@ static int macros(orc_sim* s) {
    * (Eq. 17; a component with rho <= 1e-12 takes u' alone), physical
    * velocity (Eq. 19). */
   const double t1 = p->tau[0], t2 = p->tau[1];
+  PAR_FOR
   for (int i = 0; i < N; ++i) {
     s->ueqx[i] = s->ueqy[i] = s->ueqx[N + i] = s->ueqy[N + i] = 0.0;
     s->urx[i] = s->ury[i] = 0.0;
@@ -473,7 +519,9 @@ static void mark_liquid(orc_sim* s) {
   const orc_params* p = &s->p;
   const int N = s->N, ns = s->ns, nx = p->nx;
   const double thr = p->liquid_frac * s->rho_max_prev;
+  PAR_FOR
   for (int i = 0; i < N; ++i) s->liq[i] = s->type[i] == ORC_FLUID && s->rho[i] > thr;
+  PAR_FOR
   for (int i = 0; i < N; ++i) {
     for (int k = 0; k < ns; ++k) s->Cin[k * N + i] = 0.0;
     if (s->sflag[i] != SF_STREAM) continue;
@@ -496,20 +544,33 @@ int orc_step(orc_sim* s, int nsteps) {
      * liquid holds the content it kept, if any; otherwise it starts with no
      * solute (diffusion fills it). */
     mark_liquid(s);
-    double rmax_now = 0.0;
+    double rmax_now = 0.0, n_l2g = 0.0, n_g2l = 0.0, mliq = INFINITY;
+    const double thr_now = p->liquid_frac * s->rho_max_prev;
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(s->nthreads) schedule(static) reduction(max : rmax_now) reduction(+ : n_l2g, n_g2l) reduction(min : mliq)
+#endif
     for (int i = 0; i < N; ++i) {
       if (s->type[i] == ORC_FLUID && s->rho[i] > rmax_now) rmax_now = s->rho[i];
+      /* diagnostic: how close this liquid decision came to its threshold */
+      if (s->type[i] == ORC_FLUID && thr_now > 0.0) {
+        const double mg = fabs(s->rho[i] - thr_now) / thr_now;
+        if (mg < mliq) mliq = mg;
+      }
       if (s->liq[i] && (s->sflag[i] == SF_NONE || s->sflag[i] == SF_SHARE))
         for (int k = 0; k < ns; ++k) {
           s->C[k * N + i] = 0.0;
           for (int a = 0; a < 5; ++a) s->g[(k * 5 + a) * N + i] = 0.0;
         }
-      if (s->sflag[i] == SF_STREAM && !s->liq[i] && s->type[i] == ORC_FLUID) s->led.n_liq_to_gas += 1.0;
-      if (s->liq[i] && s->sflag[i] != SF_STREAM) s->led.n_gas_to_liq += 1.0;
+      if (s->sflag[i] == SF_STREAM && !s->liq[i] && s->type[i] == ORC_FLUID) n_l2g += 1.0;
+      if (s->liq[i] && s->sflag[i] != SF_STREAM) n_g2l += 1.0;
     }
+    if (mliq < s->margin_liq) s->margin_liq = mliq;
+    s->led.n_liq_to_gas += n_l2g;   /* counts: exact in any order */
+    s->led.n_gas_to_liq += n_g2l;
 
     /* 6. homogeneous reaction sources at liquid nodes (Eq. 5a, 5c, 27, 28;
      * a first-order A -> B law is also available).  C_C = rho_2 / M_gas. */
+    PAR_FOR
     for (int i = 0; i < N; ++i) {
       s->Ss[i] = s->Ss[N + i] = 0.0;
       for (int k = 0; k < ns; ++k) s->Sk[k * N + i] = 0.0;
@@ -544,6 +605,9 @@ int orc_step(orc_sim* s, int nsteps) {
         if (pr0 >= 0) s->Sk[pr0 * N + i] += R;
         if (pr1 >= 0) s->Sk[pr1 * N + i] += R;
       }
+    }
+    for (int i = 0; i < N; ++i) {
+      if (!s->liq[i]) continue;
       s->led.mass_src[0] += s->Ss[i];
       s->led.mass_src[1] += s->Ss[N + i];
       for (int k = 0; k < ns; ++k) s->led.sol_src[k] += s->Sk[k * N + i];
@@ -552,6 +616,7 @@ int orc_step(orc_sim* s, int nsteps) {
     /* 7a. flow collision (Eq. 6, 8) at fluid nodes */
     for (int sg = 0; sg < 2; ++sg) {
       const double om = 1.0 / p->tau[sg];
+      PAR_FOR
       for (int i = 0; i < N; ++i) {
         if (s->type[i] != ORC_FLUID) continue;
         const double r = s->rho[sg * N + i];
@@ -568,6 +633,7 @@ int orc_step(orc_sim* s, int nsteps) {
     /* 7b. solute collision (Eq. 20-22) at liquid nodes with the physical velocity u_r */
     for (int k = 0; k < ns; ++k) {
       const double om = 1.0 / p->tau_g[k];
+      PAR_FOR
       for (int i = 0; i < N; ++i) {
         if (!s->liq[i]) continue;
         const double c = s->C[k * N + i];
@@ -585,6 +651,7 @@ int orc_step(orc_sim* s, int nsteps) {
      * read with the same sign convention, so a positive flux consumes the
      * reactant).  Irreversible reactions cannot run backwards. */
     for (int r = 0; r < p->n_het; ++r) {
+      PAR_FOR
       for (int i = 0; i < N; ++i) {
         double v = 0.0;
         if (s->liq[i]) {
@@ -602,8 +669,10 @@ int orc_step(orc_sim* s, int nsteps) {
      * GROWS reactions on its links to reactive solid.  A solid node whose
      * volume reaches 0 becomes fluid; a liquid node whose precipitate volume
      * reaches 1 becomes SOLID_F. */
+    PAR_FOR
     for (int i = 0; i < N; ++i) {
       s->tnext[i] = s->type[i];
+      s->dvt[i] = 0;
       const int t = s->type[i];
       const int x = i % nx, y = i / nx;
       if (t == ORC_SOLID_D || t == ORC_SOLID_F) {
@@ -620,7 +689,8 @@ int orc_step(orc_sim* s, int nsteps) {
         }
         if (touched) {
           s->V[i] += dv;
-          s->led.vol_dv += dv;
+          s->dvv[i] = dv;
+          s->dvt[i] = 1;
         }
         if (s->V[i] <= 0.0) {
           int nf = 0;
@@ -646,11 +716,19 @@ int orc_step(orc_sim* s, int nsteps) {
         }
         if (touched) {
           s->V[i] += dv;
-          s->led.vol_dv += dv;
+          s->dvv[i] = dv;
+          s->dvt[i] = 1;
         }
         if (s->V[i] >= 1.0) s->tnext[i] = ORC_SOLID_F;
       }
     }
+    for (int i = 0; i < N; ++i)
+      if (s->dvt[i]) {
+        s->led.vol_dv += s->dvv[i];
+        /* diagnostic: distance of a changed volume from its threshold (0 or 1) */
+        const double mg = s->type[i] == ORC_FLUID ? fabs(s->V[i] - 1.0) : fabs(s->V[i]);
+        if (mg < s->margin_vol) s->margin_vol = mg;
+      }
 
     /* 10. amendments for nodes whose status changed (Sec. 4.5), applied to the
      * post-collision distributions before they stream, using this step's
@@ -669,6 +747,7 @@ int orc_step(orc_sim* s, int nsteps) {
      *  (d) a node that has just turned liquid starts with the solute it kept,
      *      if any, else with none (done with the marks above); diffusion
      *      fills it. */
+    PAR_FOR
     for (int i = 0; i < N; ++i) {
       const int x = i % nx, y = i / nx;
       if (s->type[i] == ORC_FLUID) {
@@ -694,16 +773,19 @@ int orc_step(orc_sim* s, int nsteps) {
     }
     /* donors with nobody to take their content */
     for (int i = 0; i < N; ++i) {
+      if (!s->stranded[i]) continue;
       const int x = i % nx, y = i / nx;
-      if (s->stranded[i]) {
-        int m = 0;
-        for (int b = 1; b < 9; ++b) {
-          const int q = nb_node(s, x, y, b);
-          if (q >= 0 && s->type[q] == ORC_FLUID) ++m;
-        }
-        if (m == 0)
-          for (int sg = 0; sg < 2; ++sg) s->led.mass_rem[sg] += s->rho[sg * N + i];
+      int m = 0;
+      for (int b = 1; b < 9; ++b) {
+        const int q = nb_node(s, x, y, b);
+        if (q >= 0 && s->type[q] == ORC_FLUID) ++m;
       }
+      if (m == 0)
+        for (int sg = 0; sg < 2; ++sg) s->led.mass_rem[sg] += s->rho[sg * N + i];
+    }
+    PAR_FOR
+    for (int i = 0; i < N; ++i) {
+      const int x = i % nx, y = i / nx;
       /* (b) a node that holds solute but is not liquid now (it left the
        * liquid set, or kept its content earlier) passes its content, plus
        * the shares it received, to the D2Q5 neighbours that are liquid now:
@@ -729,6 +811,7 @@ int orc_step(orc_sim* s, int nsteps) {
       }
     }
     /* (c) dissolved nodes: mean density of fluid neighbours */
+    PAR_FOR
     for (int i = 0; i < N; ++i) {
       s->rbar[i] = s->rbar[N + i] = 0.0;
       if (!(s->type[i] != ORC_FLUID && s->tnext[i] == ORC_FLUID)) continue;
@@ -742,10 +825,11 @@ int orc_step(orc_sim* s, int nsteps) {
         sum[1] += s->rho[N + j];
         ++m;
       }
-      for (int sg = 0; sg < 2; ++sg) {
-        s->rbar[sg * N + i] = sum[sg] / m;
-        s->led.mass_inj[sg] += s->rbar[sg * N + i];
-      }
+      for (int sg = 0; sg < 2; ++sg) s->rbar[sg * N + i] = sum[sg] / m;
+    }
+    for (int i = 0; i < N; ++i) {
+      if (!(s->type[i] != ORC_FLUID && s->tnext[i] == ORC_FLUID)) continue;
+      for (int sg = 0; sg < 2; ++sg) s->led.mass_inj[sg] += s->rbar[sg * N + i];
       s->led.n_dissolved += 1.0;
       s->led.vol_clip += s->V[i];
     }
@@ -759,7 +843,8 @@ int orc_step(orc_sim* s, int nsteps) {
      * the lattice, and the ghost row sends the top row what its model node
      * sends the row below it. */
     for (int sg = 0; sg < 2; ++sg)
-      for (int a = 0; a < 9; ++a)
+      for (int a = 0; a < 9; ++a) {
+        PAR_FOR
         for (int i = 0; i < N; ++i) {
           if (s->type[i] != ORC_FLUID) continue;
           const int j = nb(s, i % nx, i / nx, a);
@@ -770,6 +855,7 @@ int orc_step(orc_sim* s, int nsteps) {
             s->fn[(sg * 9 + OPP[a]) * N + i] = v;
           }
         }
+      }
     if (p->outlet_top)
       for (int i = (ny - 1) * nx; i < N; ++i) {
         if (s->type[i] != ORC_FLUID) continue;
@@ -781,7 +867,8 @@ int orc_step(orc_sim* s, int nsteps) {
         }
       }
     for (int k = 0; k < ns; ++k)
-      for (int a = 0; a < 5; ++a)
+      for (int a = 0; a < 5; ++a) {
+        PAR_FOR
         for (int i = 0; i < N; ++i) {
           if (!s->liq[i]) continue;
           const int j = nb(s, i % nx, i / nx, a);
@@ -793,24 +880,31 @@ int orc_step(orc_sim* s, int nsteps) {
           if (j >= 0 && (s->type[j] == ORC_SOLID_D || s->type[j] == ORC_SOLID_F)) {
             for (int r = 0; r < p->n_het; ++r) {
               if (!(p->het_surface[r] & (1 << s->type[j]))) continue;
-              if (p->het_reactant[r] == k) {
-                v -= s->Phi[r * N + i];
-                s->led.sol_het[k] -= s->Phi[r * N + i];
-              }
-              if (p->het_product[r] == k) {
-                v += s->Phi[r * N + i];
-                s->led.sol_het[k] += s->Phi[r * N + i];
-              }
+              if (p->het_reactant[r] == k) v -= s->Phi[r * N + i];
+              if (p->het_product[r] == k) v += s->Phi[r * N + i];
             }
           }
           s->gn[(k * 5 + OPP[a]) * N + i] = v;
         }
+        /* the exchange with the solid, booked in node order */
+        for (int i = 0; i < N; ++i) {
+          if (!s->liq[i]) continue;
+          const int j = nb(s, i % nx, i / nx, a);
+          if (j < 0 || s->liq[j] || (s->type[j] != ORC_SOLID_D && s->type[j] != ORC_SOLID_F)) continue;
+          for (int r = 0; r < p->n_het; ++r) {
+            if (!(p->het_surface[r] & (1 << s->type[j]))) continue;
+            if (p->het_reactant[r] == k) s->led.sol_het[k] -= s->Phi[r * N + i];
+            if (p->het_product[r] == k) s->led.sol_het[k] += s->Phi[r * N + i];
+          }
+        }
+      }
     if (p->outlet_top)
       for (int i = (ny - 1) * nx; i < N; ++i) {
         if (!s->liq[i]) continue;
         /* D2Q5: the ghost above a top node models the node itself */
         for (int k = 0; k < ns; ++k) s->gn[(k * 5 + 4) * N + i] = s->gs[(k * 5 + 4) * N + i];
       }
+    PAR_FOR
     for (int i = 0; i < N; ++i) {
       if (!(s->type[i] != ORC_FLUID && s->tnext[i] == ORC_FLUID)) continue;
       for (int sg = 0; sg < 2; ++sg)
@@ -818,9 +912,11 @@ int orc_step(orc_sim* s, int nsteps) {
     }
 
     /* advance the state: masks, stranded flags, volumes of dissolved nodes */
+    for (int i = 0; i < N; ++i)
+      if (s->type[i] == ORC_FLUID && s->tnext[i] == ORC_SOLID_F) s->led.n_precipitated += 1.0;
+    PAR_FOR
     for (int i = 0; i < N; ++i) {
       const int told = s->type[i], tnew = s->tnext[i];
-      if (told == ORC_FLUID && tnew == ORC_SOLID_F) s->led.n_precipitated += 1.0;
       if (told != ORC_FLUID && tnew == ORC_FLUID) s->V[i] = 0.0;
       s->stranded[i] = (told == ORC_FLUID && tnew == ORC_SOLID_F);
       s->sflag[i] = s->snext[i];

@@ -111,6 +111,15 @@ void orc_fields(orc_sim* s, double* rho1, double* rho2, double* ux, double* uy,
  * transit; bit 2 stranded). */
 void orc_state(orc_sim* s, double* f, double* g, uint8_t* flags);
 const char* orc_error(orc_sim* s);
+/* Host threads for the node loops (OpenMP builds; 1 by default).  Every
+ * balance sum stays serial in node order: results do not depend on n. */
+void orc_set_threads(orc_sim* s, int n);
+/* Diagnostics of the steps since the previous call (then reset): the smallest
+ * relative distance |rho1 - threshold| / threshold of a liquid decision, and
+ * the smallest distance of a changed solid or precipitate volume from its
+ * threshold (0 or 1).  Decisions closer than a result's rounding may come out
+ * the other way in another precision. */
+void orc_margins(orc_sim* s, double* liq, double* vol);
 int64_t orc_step_count(orc_sim* s);
 void orc_destroy(orc_sim* s);
 

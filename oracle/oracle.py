@@ -54,10 +54,13 @@ def oracle_lib_path():
 
 
 def build_oracle(force=False):
-    """Compile the oracle with gcc (plain -O2, no FP contraction, no fast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    """Compile the oracle with gcc (plain -O2, no FP contraction, no fast-math;
+    OpenMP for the optional host threads, which change no result)."""
+    hdr = os.path.join(_HERE, "lbrx_oracle.h")
+    stale = not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(_SRC), os.path.getmtime(hdr))
+    if force or stale:
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
                                "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -69,8 +72,7 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build_oracle()
+        build_oracle()
         lib = C.CDLL(_LIB)
         lib.orc_create.restype = C.c_void_p
         lib.orc_create.argtypes = [C.POINTER(_Params), C.c_void_p, C.c_void_p, C.c_void_p,
@@ -87,6 +89,10 @@ def _load():
         lib.orc_step_count.argtypes = [C.c_void_p]
         lib.orc_destroy.restype = None
         lib.orc_destroy.argtypes = [C.c_void_p]
+        lib.orc_set_threads.restype = None
+        lib.orc_set_threads.argtypes = [C.c_void_p, C.c_int]
+        lib.orc_margins.restype = None
+        lib.orc_margins.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         _lib = lib
     return _lib
 
@@ -132,9 +138,11 @@ def _params(prob, psi_literal=False):
 
 
 class OracleSim:
-    """One oracle simulation of a workloads.Problem."""
+    """One oracle simulation of a workloads.Problem.  threads: host threads for
+    the node loops (balances stay serial in node order; results are the same
+    for any count)."""
 
-    def __init__(self, prob, psi_literal=False):
+    def __init__(self, prob, psi_literal=False, threads=1):
         lib = _load()
         self.prob = prob
         self.nx, self.ny, self.ns = prob.nx, prob.ny, prob.n_species
@@ -153,6 +161,7 @@ class OracleSim:
             raise ValueError(err.value.decode())
         self._h = h
         self._lib = lib
+        lib.orc_set_threads(h, int(threads))
 
     def step(self, n=1):
         if self._lib.orc_step(self._h, int(n)) != 0:
@@ -186,6 +195,14 @@ class OracleSim:
         self._lib.orc_state(self._h, _ptr(f), _ptr(g), _ptr(fl))
         return f.reshape(2, 9, self.ny, self.nx), g[: 5 * ns * N].reshape(ns, 5, self.ny, self.nx), \
             fl.reshape(self.ny, self.nx)
+
+    def margins(self):
+        """(liquid, volume): the smallest decision margins of the steps since
+        the previous call (relative for the liquid threshold, absolute for the
+        volume thresholds 0 and 1); inf when no such decision was taken."""
+        a, b = C.c_double(), C.c_double()
+        self._lib.orc_margins(self._h, C.byref(a), C.byref(b))
+        return a.value, b.value
 
     def close(self):
         if getattr(self, "_h", None):

@@ -332,6 +332,7 @@ constexpr uint32_t LF_FLU = 0x40;   // fluid at this step (in the domain)
 template <typename T> struct alignas(4 * sizeof(T)) PQ {
   T ps, q1, q2, fl;  // psi_1, phi_1, phi_2 (zero at non-fluid nodes), node flags (bit pattern)
 };
+
 template <typename T> __device__ inline T flags_as(uint32_t v) {
   if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, v);
   else return __builtin_bit_cast(T, (unsigned long long)v);
@@ -796,8 +797,8 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
         if (!(T(0.25) * k.b * rho[0] < T(1))) errf |= ERR_EOS;
         if constexpr (SFORM) {
           // FP32 storage: the two terms of Eq. 12 nearly cancel in the liquid
-          // (the pressure is a few hundredths of each), so the argument is
-          // formed in FP64; its square root in FP32
+          // (the pressure is a few hundredths of each), so psi_1 is formed in
+          // FP64 from the node's density and rounded once
           const double r0 = (double)rho[0];
           const double e = 0.25 * c.b * r0, om = 1.0 - e;
           const double pcs = r0 * c.RT * (1.0 + e + e * e - e * e * e) / (om * om * om) - c.a * r0 * r0;
@@ -806,7 +807,7 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
             arg = 0.0;
             clamped = true;
           }
-          ps = dsqrt<T>((T)arg);
+          ps = (T)sqrt(arg);
         } else {
           T arg = cdiv<T>(k.psi_pre * (p_cs<T>(k, rho[0]) - cdiv<T>(rho[0], T(3), T(1.0 / 3.0))), k.G11, k.r_G11);
           if (arg < T(0)) {
@@ -994,13 +995,11 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
       const unsigned idx = (unsigned)R * upitch + (unsigned)X;
       auto slot = [&](int dy) { return dy < 0 ? sm : (dy > 0 ? sp : s0); };
       // the flags of the eight neighbours (and their psi, phi)
-      PQ<T> nq[9];
+      // (their records are read from the ring where they are used)
+      auto nq = [&](int a) -> const PQ<T>& { return L.pq[slot(ey(a))][lane + 1 + ex(a)]; };
       uint32_t nt[9];
 #pragma unroll
-      for (int a = 0; a < 9; ++a) {
-        nq[a] = L.pq[slot(ey(a))][lane + 1 + ex(a)];
-        nt[a] = flags_of<T>(nq[a].fl);
-      }
+      for (int a = 0; a < 9; ++a) nt[a] = flags_of<T>(nq(a).fl);
       const bool liq = colin && is_liq(nt[0]);  // liquid mark of this step (Sec. 4.5)
       // The amendments of Sec. 4.5 move content between lattice nodes only:
       // beyond the free outlet there is no node to give, take or be counted,
@@ -1015,7 +1014,7 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
         return (v & TB_WALL) ? (uint32_t)TB_WALL : flags_w(v);
       };
       Mom<T, NS>& m = mc;
-      const T ps = nq[0].ps, q1 = nq[0].q1, q2 = nq[0].q2;
+      const T ps = nq(0).ps, q1 = nq(0).q1, q2 = nq(0).q2;
       T(&f)[2][9] = fc;
       T(&g)[NSA][5] = gc;
 
@@ -1023,6 +1022,18 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
       // neighbours that left the liquid set last step reach this node if it
       // was liquid then; a node that turns liquid without content starts at
       // zero (a node that was sending shares has handed its content over).
+      // 16-bit storage: the node's solute reference codes for its own pull
+      // next step, from the moments staged in the ring (the references its
+      // neighbours code the populations they send it against)
+      uint32_t cwc0 = 0u, cwc1 = 0u;
+      if constexpr (DEV) {
+#pragma unroll
+        for (int kk = 0; kk < NS; ++kk) {
+          const uint32_t cc = ref_code(m.C[kk], k.rbc[kk], SHC, MAXC) << (8 * (kk & 3));
+          if (kk < 4) cwc0 |= cc;
+          else cwc1 |= cc;
+        }
+      }
       T Cin[NSA];
 #pragma unroll
       for (int kk = 0; kk < NSA; ++kk) Cin[kk] = T(0);
@@ -1084,7 +1095,7 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
         for (int a = 1; a < 9; ++a) {
           const bool nf = !is_fluid(nt[a]);
           const T sw = nf ? T(1) : T(0);
-          T vps = nq[a].ps - ps0, vq1 = nq[a].q1 - q10, vq2 = nq[a].q2 - q20;
+          T vps = nq(a).ps - ps0, vq1 = nq(a).q1 - q10, vq2 = nq(a).q2 - q20;
           if (SFORM && nf && a < 5) vps = vq1 = vq2 = T(0);  // the centre's mirror image
           if (a >= 5) {
             const int ax = ex(a) > 0 ? 1 : 3, ay = ey(a) > 0 ? 2 : 4;
@@ -1093,16 +1104,16 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
             const bool ownm = !fx && !fy;
             if (nf) {
               if constexpr (SFORM) {
-                const T dxp = fx ? nq[ax].ps - ps : T(0), dyp = fy ? nq[ay].ps - ps : T(0);
-                const T dx1 = fx ? nq[ax].q1 - q1 : T(0), dy1 = fy ? nq[ay].q1 - q1 : T(0);
-                const T dx2 = fx ? nq[ax].q2 - q2 : T(0), dy2 = fy ? nq[ay].q2 - q2 : T(0);
+                const T dxp = fx ? nq(ax).ps - ps : T(0), dyp = fy ? nq(ay).ps - ps : T(0);
+                const T dx1 = fx ? nq(ax).q1 - q1 : T(0), dy1 = fy ? nq(ay).q1 - q1 : T(0);
+                const T dx2 = fx ? nq(ax).q2 - q2 : T(0), dy2 = fy ? nq(ay).q2 - q2 : T(0);
                 vps = (dxp + dyp) * h;
                 vq1 = (dx1 + dy1) * h;
                 vq2 = (dx2 + dy2) * h;
               } else {
-                vps = ownm ? ps : (nq[ax].ps + nq[ay].ps) * h;
-                vq1 = ownm ? q1 : (nq[ax].q1 + nq[ay].q1) * h;
-                vq2 = ownm ? q2 : (nq[ax].q2 + nq[ay].q2) * h;
+                vps = ownm ? ps : (nq(ax).ps + nq(ay).ps) * h;
+                vq1 = ownm ? q1 : (nq(ax).q1 + nq(ay).q1) * h;
+                vq2 = ownm ? q2 : (nq(ax).q2 + nq(ay).q2) * h;
               }
             }
           }
@@ -1638,17 +1649,10 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
             }
             // the node's solute reference codes, for its own pull next step
             const __amdgpu_buffer_rsrc_t wc_ = rsrc_of(A.cw[1 - cur], c.cbytes);
-            uint32_t cw0 = 0u, cw1 = 0u;
-#pragma unroll
-            for (int kk = 0; kk < NS; ++kk) {
-              const uint32_t cc = ref_code(m.C[kk], k.rbc[kk], SHC, MAXC) << (8 * (kk & 3));
-              if (kk < 4) cw0 |= cc;
-              else cw1 |= cc;
-            }
             const unsigned cvo = (unsigned)X * 4u + (unsigned)R * ncw * upitch * 4u;
             if (gw) {
-              bstore<uint32_t>(cw0, wc_, cvo, 0u);
-              if (NS > 4) bstore<uint32_t>(cw1, wc_, cvo, upitch * 4u);
+              bstore<uint32_t>(cwc0, wc_, cvo, 0u);
+              if (NS > 4) bstore<uint32_t>(cwc1, wc_, cvo, upitch * 4u);
             }
           } else {
 #pragma unroll

@@ -2,10 +2,12 @@
 benchmark uses (same lattice generator, same kernel, default item shape).
 
 The 1024 x 512 porous medium is compared field by field against the FP64
-oracle in FP64 and FP32; the 4096 x 4096 roofline workload is compared field
-by field for a few FP32 steps (the oracle needs about 4 s per step there) and
-then checked, after many more GPU steps, on properties that hold at any size:
-the mass balance closes with the ledger and the masks stay consistent.
+oracle (run on the host's cores; its balances stay serial, so the result is
+the single-thread one) in FP64 and FP32 through 1000 steps, and the 16-bit
+storage forms are measured against it per field; the 4096 x 4096 roofline
+workload is compared field by field for a few FP32 steps and then checked,
+after many more GPU steps, on properties that hold at any size: the mass
+balance closes with the ledger and the masks stay consistent.
 """
 import os
 import sys
@@ -28,6 +30,43 @@ def _lbrx():
     return Lbrx
 
 
+THREADS = max(1, min(16, os.cpu_count() or 1))
+CHECK_STEPS = (10, 1000)
+# relative shift of the liquid threshold that brackets decisions taken too
+# close to it for another precision to reproduce (Sec. 4.5 marks are a step
+# function of the density)
+THR_SHIFT = 1e-6
+
+
+@pytest.fixture(scope="module")
+def porous_oracle():
+    """The FP64 oracle's fields of the 1024 x 512 porous medium at steps 10
+    and 1000, and of the same run with the liquid threshold moved by
+    +-THR_SHIFT (relative): their difference is how far this workload's fields
+    move when liquid decisions within that margin go the other way."""
+    prob = W.config1()
+    runs = {}
+    for tag, lf in (("0", prob.liquid_frac), ("+", prob.liquid_frac * (1 + THR_SHIFT)),
+                    ("-", prob.liquid_frac * (1 - THR_SHIFT))):
+        o = OracleSim(prob.copy(liquid_frac=lf), threads=THREADS)
+        runs[tag] = {}
+        for n in CHECK_STEPS:
+            o.step(n - o.steps_done)
+            runs[tag][n] = o.fields()
+        o.close()
+    return prob, runs
+
+
+def _beyond_envelope(G, runs, n, key, k=None):
+    """max(|G - O| - max(|O+ - O|, |O- - O|), 0) / max|O| of one field."""
+    def get(F):
+        return F[key] if k is None else F[key][k]
+    O = get(runs["0"][n])
+    env = np.maximum(np.abs(get(runs["+"][n]) - O), np.abs(get(runs["-"][n]) - O))
+    scale = max(np.abs(O).max(), 1e-300)
+    return float(np.maximum(np.abs(get(G) - O) - env, 0.0).max() / scale)
+
+
 def _check(G, O, prob, tol, label):
     errs, masks, near = compare(G, O, prob, tol)
     print(f"[{label}] " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()) + f" masks={masks}", flush=True)
@@ -36,17 +75,76 @@ def _check(G, O, prob, tol, label):
         assert v <= tol, f"{label}: {k} error {v:.3e} > {tol:.1e}"
 
 
-@pytest.mark.parametrize("precision,steps,tol", [("f64", 40, 1e-12), ("f32", 10, 1e-5)])
-def test_porous_1024x512_full_field(precision, steps, tol):
-    """The 1024 x 512 porous medium (seed 1): every field of every node."""
-    prob = W.config1()
-    o = OracleSim(prob)
-    g = _lbrx()(prob, precision)
-    o.step(steps)
-    g.step(steps)
-    _check(g.fields(), o.fields(), prob, tol, f"porous-1024x512 {precision} {steps}")
+def test_porous_1024x512_fp64(porous_oracle):
+    """FP64 on the 1024 x 512 porous medium (seed 1): every field of every
+    node within 1e-12 at steps 10 and 1000, masks identical."""
+    prob, runs = porous_oracle
+    g = _lbrx()(prob, "f64")
+    for n in CHECK_STEPS:
+        g.step(n - g.steps_done)
+        _check(g.fields(), runs["0"][n], prob, 1e-12, f"porous-1024x512 f64 {n}")
     g.close()
-    o.close()
+
+
+# FP32 bounds on this workload after 1000 steps.  Its flow amplifies
+# rounding-level differences in a few vapour films at solid corners: the FP64
+# oracle with its stored populations rounded to FP32 once per step departs from
+# itself by 5.5e-5 in density, 9.6e-5 in velocity and 3e-2 in solid volume
+# there, a single 6e-8 change of its initial densities moves the velocity by
+# 9e-7, and the FP32 kernel with its velocities formed in FP64 lands at 3.6e-5.
+# Densities and volumes are asserted within 2e-5, velocities within 3e-5, and
+# concentrations within 1e-5 beyond the oracle's own threshold spread; every
+# field within 1e-5 at step 10.
+FP32_BOUNDS_1000 = {"rho1": 2e-5, "rho2": 2e-5, "V": 2e-5, "ux": 3e-5, "uy": 3e-5}
+
+
+def test_porous_1024x512_fp32(porous_oracle):
+    """FP32 on the 1024 x 512 porous medium at steps 10 and 1000 against the
+    FP64 oracle: masks identical, every field within 1e-5 at step 10
+    (concentrations beyond the spread that liquid decisions within 1e-6 of the
+    threshold cause in the oracle itself: the marks are a step function of
+    rho_1, and they move C by up to 3.5e-4 there), the bounds above at step
+    1000."""
+    prob, runs = porous_oracle
+    g = _lbrx()(prob, "f32")
+    for n in CHECK_STEPS:
+        g.step(n - g.steps_done)
+        G = g.fields()
+        errs, masks, near = compare(G, runs["0"][n], prob, 1e-5)
+        env = {f"C{k}": _beyond_envelope(G, runs, n, "C", k) for k in range(prob.n_species)}
+        print(f"[porous-1024x512 f32 {n}] " + " ".join(f"{k}={v:.2e}" for k, v in errs.items())
+              + " beyond-threshold-spread " + " ".join(f"{k}={v:.2e}" for k, v in env.items())
+              + f" masks={masks}", flush=True)
+        assert masks
+        for k in ("rho1", "rho2", "V", "ux", "uy"):
+            bound = 1e-5 if n < 1000 else FP32_BOUNDS_1000[k]
+            assert errs[k] <= bound, (n, k, errs[k], bound)
+        for k, v in env.items():
+            assert v <= 1e-5, (n, k, v)
+    g.close()
+
+
+@pytest.mark.parametrize("precision", ["f16dev", "bf16dev"])
+def test_porous_1024x512_16bit_storage(porous_oracle, precision):
+    """16-bit deviation storage on the 1024 x 512 porous medium against the
+    FP64 oracle, per field (max-norm relative: density, velocity, each
+    species, also beyond the oracle's threshold spread, solid volume) and
+    porosity, at steps 10 and 1000."""
+    prob, runs = porous_oracle
+    g = _lbrx()(prob, precision)
+    for n in CHECK_STEPS:
+        g.step(n - g.steps_done)
+        G, O = g.fields(), runs["0"][n]
+        errs, masks, near = compare(G, O, prob, 1e-3)
+        for k in range(prob.n_species):
+            errs[f"C{k}_beyond"] = _beyond_envelope(G, runs, n, "C", k)
+        por_g = float((G["type"] == 0).mean())
+        por_o = float((O["type"] == 0).mean())
+        errs["porosity"] = abs(por_g - por_o) / por_o
+        errs["liquid_nodes"] = float(np.abs(G["liquid"].astype(int) - O["liquid"].astype(int)).sum())
+        print(f"[porous-1024x512 {precision} {n}] " + " ".join(f"{k}={v:.2e}" for k, v in errs.items())
+              + f" masks={masks}", flush=True)
+    g.close()
 
 
 def test_porous_4096_full_field_and_balances():
@@ -56,7 +154,7 @@ def test_porous_4096_full_field_and_balances():
     component, to FP32 summation accuracy) and keep every liquid node fluid."""
     prob = W.config2()
     g = _lbrx()(prob, "f32")
-    o = OracleSim(prob)
+    o = OracleSim(prob, threads=THREADS)
     o.step(2)
     g.step(2)
     _check(g.fields(), o.fields(), prob, 1e-5, "porous-4096 f32 2")
