@@ -213,8 +213,26 @@ lbrx_status lbrx_step(lbrx_ctx* ctx, int64_t n_steps);
 /* Waits for the context's stream and reports a sticky numerical failure. */
 lbrx_status lbrx_sync(lbrx_ctx* ctx);
 
-/* Waits, then fills the caller's host buffers (FP64 whatever the precision). */
+/* Waits, then fills the caller's host buffers (FP64 whatever the precision).
+ * The first call on a context allocates its device read-out staging
+ * ((5 + n_species) planes of pitch * ny doubles plus the summed balances),
+ * which the context keeps until lbrx_destroy. */
 lbrx_status lbrx_fields(lbrx_ctx* ctx, lbrx_fields_out* out);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture elsewhere on the device, tight serving loops, harnesses that forbid
+ * allocation): lbrx_fields without any device allocation or free.  The
+ * read-out kernels stage their output in one static device array per GPU of
+ * LBRX_NOALLOC_SCRATCH_BYTES bytes (the library's; it exists on every GPU the
+ * library runs on until the process ends).  A context whose read-out needs
+ * more, (5 + n_species) * pitch * ny + 38 doubles with pitch = nx rounded up
+ * to 64, gets LBRX_E_INVAL and a message (use lbrx_fields for it).  Outputs,
+ * arguments and errors are those of lbrx_fields.  Every call on one GPU
+ * shares that GPU's array: the call clears what must start at zero, and
+ * calls that overlap on one GPU (another thread, another context's stream)
+ * race and must be serialised by the caller. */
+#define LBRX_NOALLOC_SCRATCH_BYTES (128ull << 20)
+lbrx_status lbrx_fields_noalloc(lbrx_ctx* ctx, lbrx_fields_out* out);
 
 /* Checkpoint and resume of the whole simulation state, so that a run of the
  * Sec. 4.7 procedure can stop and continue: the populations, node status

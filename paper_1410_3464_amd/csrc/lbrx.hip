@@ -31,6 +31,7 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -182,7 +183,6 @@ template <typename T> struct KArgs {
   unsigned long long* rmax;  // 3 rotating slots
   double* led;               // [nitems][NLED]
   unsigned int* err;         // [0] flags, [1] first failing node (min index)
-  double *o_r1, *o_r2, *o_ux, *o_uy, *o_C, *o_L;  // export outputs (plane-sized); o_L: liquid marks
 };
 
 // constant address space: data no store of a running kernel can change
@@ -199,6 +199,7 @@ struct LaunchArgs {
   int ninst;
   int phase0;  // single: step count mod 6
   int launch;  // batch: launches since the table was built, mod 6
+  double* out;  // read-out launches: planes rho1, rho2, ux, uy, C_0.., liquid (pitch-strided)
 };
 constexpr int TAB_INST_SHIFT = 20, TAB_PHASE_SHIFT = 17;
 constexpr uint32_t TAB_BLOCK_MASK = (1u << TAB_PHASE_SHIFT) - 1u;
@@ -1166,8 +1167,8 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
         const T ury = qdiv<T>(m.jy[0] + m.jy[1] + T(0.5) * (Fy[0] + Fy[1]), rt_);
 
         if (EXPORT) {
-          A.o_ux[idx] = (double)urx;
-          A.o_uy[idx] = (double)ury;
+          LA.out[2 * c.plane + idx] = (double)urx;
+          LA.out[3 * c.plane + idx] = (double)ury;
         } else {
           // homogeneous reactions at liquid nodes (Eq. 5a, 5c, 27, 28); the
           // species sources are the net stoichiometric coefficients times the rates
@@ -1536,19 +1537,20 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
 
       if (EXPORT) {
         if (own) {
-          A.o_r1[idx] = (double)m.rho[0];
-          A.o_r2[idx] = (double)m.rho[1];
+          double* const o = LA.out;
+          o[idx] = (double)m.rho[0];
+          o[c.plane + idx] = (double)m.rho[1];
           if (!fluid) {
-            A.o_ux[idx] = 0.0;
-            A.o_uy[idx] = 0.0;
+            o[2 * c.plane + idx] = 0.0;
+            o[3 * c.plane + idx] = 0.0;
           }
           // the solute each node holds once the shares in transit are delivered
 #pragma unroll
           for (int kk = 0; kk < NS; ++kk) {
             const T cv = sf == SF_STREAM ? m.C[kk] + Cin[kk] : (sf == SF_HOLD ? m.C[kk] : T(0));
-            A.o_C[(size_t)kk * c.plane + idx] = (double)cv;
+            o[(size_t)(4 + kk) * c.plane + idx] = (double)cv;
           }
-          A.o_L[idx] = liq ? 1.0 : 0.0;
+          o[(size_t)(4 + NS) * c.plane + idx] = liq ? 1.0 : 0.0;
         }
       } else {
         // -------------------------------------------------- own-slot stores
@@ -1802,7 +1804,7 @@ struct lbrx_ctx {
   double* led = nullptr;
   double* ledsum = nullptr;
   unsigned int* err = nullptr;
-  double* out = nullptr;  // export scratch: (5 + ns) planes
+  double* out = nullptr;  // read-out staging (read_out_doubles), allocated by the first lbrx_fields
   void* dargs = nullptr;  // this simulation's KArgs in device memory
   int cur = 0;
   int64_t steps = 0;
@@ -2128,13 +2130,6 @@ void make_args(const lbrx_ctx* x, KArgs<T>& A, const KT<T>& kt) {
   A.rmax = x->rmax;
   A.led = x->led;
   A.err = x->err;
-  const size_t plane = (size_t)x->c.plane;
-  A.o_r1 = x->out;
-  A.o_r2 = x->out ? x->out + plane : nullptr;
-  A.o_ux = x->out ? x->out + 2 * plane : nullptr;
-  A.o_uy = x->out ? x->out + 3 * plane : nullptr;
-  A.o_C = x->out ? x->out + 4 * plane : nullptr;
-  A.o_L = x->out ? x->out + (4 + (size_t)x->c.ns) * plane : nullptr;
 }
 
 // (re)writes the simulation's device-resident KArgs (synchronous copy)
@@ -2151,11 +2146,12 @@ hipError_t upload_args(lbrx_ctx* x) {
 
 size_t args_bytes(int precision) { return precision == LBRX_F64 ? sizeof(KArgs<double>) : sizeof(KArgs<float>); }
 
-void launch_one(lbrx_ctx* x, bool exporting) {
+void launch_one(lbrx_ctx* x, bool exporting, double* out = nullptr) {
   LaunchArgs L{};
   L.single = x->dargs;
   L.ninst = 0;
   L.phase0 = (int)(x->steps % 6);
+  L.out = out;
   const dim3 grid(x->c.nblocks), block(64, WPB);
   if (x->precision == LBRX_F64)
     hipLaunchKernelGGL(exporting ? x->export64 : x->step64, grid, block, 0, x->stream, L);
@@ -2630,33 +2626,37 @@ lbrx_status lbrx_load_state(lbrx_ctx* x, const void* buf, uint64_t bytes) {
   return LBRX_OK;
 }
 
-lbrx_status lbrx_fields(lbrx_ctx* x, lbrx_fields_out* o) {
-  if (!x || !o) return LBRX_E_INVAL;
-  const lbrx_status st = lbrx_sync(x);
-  if (st != LBRX_OK) return st;
+}  // extern "C"
+
+namespace {
+
+// Read-out staging of a context, in doubles: the planes of lbrx_fields_out
+// (rho1, rho2, ux, uy, every C_k, liquid marks; pitch-strided) and the summed
+// balance records.
+size_t read_out_doubles(const KConst& c) { return (5 + (size_t)c.ns) * (size_t)c.plane + NLED; }
+
+// lbrx_fields into caller buffers, with the read-out kernels writing into
+// `stage` (read_out_doubles(c) doubles of device memory).
+lbrx_status fields_into(lbrx_ctx* x, lbrx_fields_out* o, double* stage) {
   const KConst& c = x->c;
   const size_t plane = (size_t)c.plane;
-  if (!x->out) {
-    if (!ctx_alloc(x, (void**)&x->out, (5 + (size_t)c.ns) * plane * 8))
-      return set_err(x, LBRX_E_NOMEM, "device allocation of the read-out planes failed");
-    HIPCHK(x, upload_args(x));
-  }
-  HIPCHK(x, hipMemsetAsync(x->out, 0, (5 + (size_t)c.ns) * plane * 8, x->stream));
-  launch_one(x, true);
+  double* const ledsum = stage + (5 + (size_t)c.ns) * plane;
+  HIPCHK(x, hipMemsetAsync(stage, 0, (5 + (size_t)c.ns) * plane * 8, x->stream));
+  launch_one(x, true, stage);
   HIPCHK(x, hipGetLastError());
-  hipLaunchKernelGGL(k_ledger_sum, dim3(NLED), dim3(LSUM_THREADS), 0, x->stream, x->led, c.nitems, x->ledsum);
+  hipLaunchKernelGGL(k_ledger_sum, dim3(NLED), dim3(LSUM_THREADS), 0, x->stream, x->led, c.nitems, ledsum);
   HIPCHK(x, hipGetLastError());
   HIPCHK(x, hipStreamSynchronize(x->stream));
   const size_t sp = (size_t)c.pitch * 8, dp = (size_t)c.nx * 8;
   auto get2d = [&](double* dst, const double* src) -> hipError_t {
     return hipMemcpy2D(dst, dp, src, sp, dp, c.ny, hipMemcpyDeviceToHost);
   };
-  if (o->rho1) HIPCHK(x, get2d(o->rho1, x->out));
-  if (o->rho2) HIPCHK(x, get2d(o->rho2, x->out + plane));
-  if (o->ux) HIPCHK(x, get2d(o->ux, x->out + 2 * plane));
-  if (o->uy) HIPCHK(x, get2d(o->uy, x->out + 3 * plane));
+  if (o->rho1) HIPCHK(x, get2d(o->rho1, stage));
+  if (o->rho2) HIPCHK(x, get2d(o->rho2, stage + plane));
+  if (o->ux) HIPCHK(x, get2d(o->ux, stage + 2 * plane));
+  if (o->uy) HIPCHK(x, get2d(o->uy, stage + 3 * plane));
   if (o->C)
-    for (int k = 0; k < c.ns; ++k) HIPCHK(x, get2d(o->C + (size_t)k * c.nx * c.ny, x->out + (4 + k) * plane));
+    for (int k = 0; k < c.ns; ++k) HIPCHK(x, get2d(o->C + (size_t)k * c.nx * c.ny, stage + (4 + k) * plane));
   if (o->V) HIPCHK(x, get2d(o->V, x->V));
   if (o->type) {
     std::vector<uint32_t> tb((size_t)c.nx * c.ny);
@@ -2667,12 +2667,12 @@ lbrx_status lbrx_fields(lbrx_ctx* x, lbrx_fields_out* o) {
   if (o->liquid) {
     // this step's liquid marks, decided by the read-out kernel as by the step
     std::vector<double> lq((size_t)c.nx * c.ny);
-    HIPCHK(x, get2d(lq.data(), x->out + (4 + (size_t)c.ns) * plane));
+    HIPCHK(x, get2d(lq.data(), stage + (4 + (size_t)c.ns) * plane));
     for (size_t i = 0; i < lq.size(); ++i) o->liquid[i] = lq[i] != 0.0 ? 1 : 0;
   }
   if (o->ledger) {
     double l[NLED];
-    HIPCHK(x, hipMemcpy(l, x->ledsum, sizeof l, hipMemcpyDeviceToHost));
+    HIPCHK(x, hipMemcpy(l, ledsum, sizeof l, hipMemcpyDeviceToHost));
     static_assert(sizeof(lbrx_ledger) == NLED * sizeof(double), "ledger layout");
     l[NLED - 1] = (double)x->steps;
     std::memcpy(o->ledger, l, sizeof l);
@@ -2690,6 +2690,62 @@ lbrx_status lbrx_fields(lbrx_ctx* x, lbrx_fields_out* o) {
     *o->rho_max = m;
   }
   return LBRX_OK;
+}
+
+// Read-out staging for lbrx_fields_noalloc: one static array per GPU (each
+// device holds its own copy from the time the library is loaded until the
+// process ends).  Host code never uses the array's name as an address: its
+// device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t NOALLOC_DOUBLES = LBRX_NOALLOC_SCRATCH_BYTES / sizeof(double);
+__device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+
+double* scratch_of_device(int dev, hipError_t& e) {
+  e = hipSuccess;
+  if (dev < 0 || dev >= MAX_DEVICES) {
+    e = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));  // the current device is `dev`
+    if (e != hipSuccess) return nullptr;
+    g_scratch_ptr[dev] = (double*)ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+lbrx_status lbrx_fields(lbrx_ctx* x, lbrx_fields_out* o) {
+  if (!x || !o) return LBRX_E_INVAL;
+  const lbrx_status st = lbrx_sync(x);
+  if (st != LBRX_OK) return st;
+  if (!x->out && !ctx_alloc(x, (void**)&x->out, read_out_doubles(x->c) * 8))
+    return set_err(x, LBRX_E_NOMEM, "device allocation of the read-out planes failed");
+  return fields_into(x, o, x->out);
+}
+
+lbrx_status lbrx_fields_noalloc(lbrx_ctx* x, lbrx_fields_out* o) {
+  if (!x || !o) return LBRX_E_INVAL;
+  if (read_out_doubles(x->c) > NOALLOC_DOUBLES) {
+    char buf[200];
+    snprintf(buf, sizeof buf,
+             "lbrx_fields_noalloc: the read-out of this lattice needs %zu bytes, more than the %zu-byte static "
+             "array (use lbrx_fields)", read_out_doubles(x->c) * 8, (size_t)LBRX_NOALLOC_SCRATCH_BYTES);
+    return set_err(x, LBRX_E_INVAL, buf);
+  }
+  const lbrx_status st = lbrx_sync(x);  // (selects the context's device)
+  if (st != LBRX_OK) return st;
+  hipError_t e;
+  double* stage = scratch_of_device(x->device, e);
+  if (!stage) return set_err(x, LBRX_E_DEVICE, std::string("hipGetSymbolAddress of the read-out array: ") + hipGetErrorString(e));
+  return fields_into(x, o, stage);
 }
 
 int64_t lbrx_step_count(const lbrx_ctx* x) { return x ? x->steps : -1; }

@@ -25,7 +25,7 @@ STATUS = {0: "LBRX_OK", 1: "LBRX_E_INVAL", 2: "LBRX_E_NOMEM", 3: "LBRX_E_DEVICE"
           4: "LBRX_E_UNSTABLE", 5: "LBRX_E_STATE"}
 
 # every symbol include/lbrx.h declares
-SYMBOLS = ("lbrx_create", "lbrx_create_error", "lbrx_step", "lbrx_sync", "lbrx_fields",
+SYMBOLS = ("lbrx_create", "lbrx_create_error", "lbrx_step", "lbrx_sync", "lbrx_fields", "lbrx_fields_noalloc",
            "lbrx_step_count", "lbrx_stream", "lbrx_destroy", "lbrx_last_error",
            "lbrx_status_string", "lbrx_batch_create", "lbrx_batch_step", "lbrx_batch_last_error",
            "lbrx_batch_destroy", "lbrx_state_bytes", "lbrx_save_state", "lbrx_load_state")
@@ -138,6 +138,8 @@ def load_library(path=LIB_PATH):
     lib.lbrx_sync.argtypes = [C.c_void_p]
     lib.lbrx_fields.restype = C.c_int
     lib.lbrx_fields.argtypes = [C.c_void_p, C.POINTER(FieldsOut)]
+    lib.lbrx_fields_noalloc.restype = C.c_int
+    lib.lbrx_fields_noalloc.argtypes = [C.c_void_p, C.POINTER(FieldsOut)]
     lib.lbrx_step_count.restype = C.c_int64
     lib.lbrx_step_count.argtypes = [C.c_void_p]
     lib.lbrx_stream.restype = C.c_void_p
@@ -266,7 +268,8 @@ class Lbrx:
     def stream(self):
         return self._lib.lbrx_stream(self._h)
 
-    def fields(self):
+    def fields(self, noalloc=False):
+        """The fields in FP64 (lbrx_fields; lbrx_fields_noalloc with noalloc=True)."""
         N, ny, nx, ns = self.nx * self.ny, self.ny, self.nx, self.ns
         r1, r2, ux, uy, V = (np.zeros(N) for _ in range(5))
         Cc = np.zeros(max(ns, 1) * N)
@@ -276,7 +279,8 @@ class Lbrx:
         rmax = np.zeros(1)
         o = FieldsOut(_ptr(r1), _ptr(r2), _ptr(ux), _ptr(uy), _ptr(Cc), _ptr(V), _ptr(t), _ptr(lq),
                       _ptr(led), _ptr(rmax))
-        self._check(self._lib.lbrx_fields(self._h, C.byref(o)))
+        fn = self._lib.lbrx_fields_noalloc if noalloc else self._lib.lbrx_fields
+        self._check(fn(self._h, C.byref(o)))
         out = dict(rho1=r1.reshape(ny, nx), rho2=r2.reshape(ny, nx), ux=ux.reshape(ny, nx),
                    uy=uy.reshape(ny, nx), C=Cc[: ns * N].reshape(ns, ny, nx), type=t.reshape(ny, nx),
                    liquid=lq.reshape(ny, nx), V=V.reshape(ny, nx), rho_max_prev=float(rmax[0]))
