@@ -146,6 +146,12 @@ struct KConst {
   int nhet;
   int xre[LBRX_MAX_RXN], xpr[LBRX_MAX_RXN], xsurf[LBRX_MAX_RXN], xmode[LBRX_MAX_RXN], xirrev[LBRX_MAX_RXN];
   double xkap[LBRX_MAX_RXN], xCeq[LBRX_MAX_RXN], xmvol[LBRX_MAX_RXN];
+  // per reactive solid type (q = 0: SOLID_D, 1: SOLID_F) and reaction: the
+  // precipitate volume per unit flux a liquid node collects on a link to it
+  // (GROWS reactions on that surface, else 0), and the solid volume change per
+  // unit flux on a link from a liquid node (-Vbar CONSUMES, +Vbar MINERAL, else 0)
+  double xgv[2][LBRX_MAX_RXN], xsv[2][LBRX_MAX_RXN];
+  int xgrow[2], xsolid[2];  // some reaction of that kind runs on that surface
 };
 
 // Per-precision copies of the real constants (and reciprocals, used by the FP32
@@ -159,6 +165,9 @@ template <typename T> struct KT {
       r_hMgas[LBRX_MAX_RXN];
   T xkap[LBRX_MAX_RXN], xCeq[LBRX_MAX_RXN];
   T hnu[LBRX_MAX_RXN][LBRX_MAX_SPECIES];  // net stoichiometric coefficient of species k in reaction r
+  // link flux of a heterogeneous reaction: +1 for its product, -1 for its
+  // reactant, per reactive solid type whose surface it runs on (else 0)
+  T xnu[2][LBRX_MAX_RXN][LBRX_MAX_SPECIES];
   // FP32 solute weights of Eq. 22 as stored: J1' on a 2^-26 grid and
   // J0' = 1 - 4 J1', so that the weights sum to one exactly; 1 / (2 J1'), 1 / J1'
   T Jp0[LBRX_MAX_SPECIES], Jp1[LBRX_MAX_SPECIES], hJ[LBRX_MAX_SPECIES], iJ1[LBRX_MAX_SPECIES];
@@ -367,6 +376,12 @@ template <typename T> struct alignas(2 * sizeof(T)) RF {
   T r1, r2;  // reference densities a population written to this node is coded against
 };
 
+// the change of a reactive solid's volume over one link from a liquid node
+// (Eq. 33, A2), for a SOLID_D and a SOLID_F node at the other end
+struct alignas(16) VS {
+  double d, f;
+};
+
 template <typename T, int NS, int SM> struct WaveLds {
   static constexpr int NSA = NS > 0 ? NS : 1;
   // flow reference rows (FP32 and 16-bit storage), solute reference rows (16-bit storage)
@@ -380,12 +395,14 @@ template <typename T, int NS, int SM> struct WaveLds {
   T r1[3][SW + 2], r2[3][SW + 2];
   T C[NSA][3][SW + 2];
   RF<T> rf[NRF][SW + 2];
+  VS vs[3][SW + 2];
   T Cf[NSA][NCF][SW + 2];
   // halo columns (left, right) for rows y0 - 1 .. y0 + H
   PQ<T> hpq[2][HMAX + 2];
   T hr1[2][HMAX + 2], hr2[2][HMAX + 2];
   T hC[NSA][2][HMAX + 2];
   RF<T> hrf[NHF][HMAX + 2];
+  VS hvs[2][HMAX + 2];
   T hCf[NSA][NHC][HMAX + 2];
   double rare[NRARE_SLOTS];
 };
@@ -555,11 +572,15 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
   static_assert(!DEV || std::is_same<T, float>::value, "16-bit storage computes in FP32");
   const KAS KConst& c = A.c;
   const KAS KT<T>& k = A.k;
+  // the wavefront's index in the workgroup (one row of 64 lanes each), kept
+  // uniform so that the item's rows, bounds and phases stay in scalar
+  // registers and its control flow in scalar branches
+  const int wv = WPB == 1 ? 0 : __builtin_amdgcn_readfirstlane((int)threadIdx.y);
   __shared__ WaveLds<T, NS, SM> s_all[WPB];
-  WaveLds<T, NS, SM>& L = s_all[threadIdx.y];
+  WaveLds<T, NS, SM>& L = s_all[wv];
   const int lane = threadIdx.x;
 
-  const int item = blk * WPB + (int)threadIdx.y;
+  const int item = blk * WPB + wv;
   if (item >= c.nitems) return;  // whole wavefront
   const int sx = item % c.strips, sy = item / c.strips;
   const int x0 = sx * SW, y0 = sy * c.seg_rows;
@@ -837,6 +858,30 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
     }
   };
 
+  // A liquid node's contribution to the volume of a reactive solid D2Q5
+  // neighbour (Eq. 33, A2): the flux of every reaction on that solid's surface
+  // from the node's concentration (zero for a liquid node without content),
+  // times -Vbar (CONSUMES) or +Vbar (MINERAL), summed in reaction order.
+  // Formed once per node where its moments are staged, so that a solid node
+  // adds up its neighbours' values.
+  const bool any_xsolid = NS > 0 && (c.xsolid[0] || c.xsolid[1]);
+  auto solid_dv = [&](bool liqn, uint32_t w, const Mom<T, NS>& m) -> VS {
+    VS o{0.0, 0.0};
+    if (any_xsolid) {
+      const int nsf = sf_of(w);
+      const bool has = nsf == SF_STREAM || nsf == SF_HOLD;
+      for (int r = 0; r < c.nhet; ++r) {
+        const T cr = sel<NS>(m.C, c.xre[r]);
+        T v = k.xkap[r] * ((has ? cr : T(0)) - k.xCeq[r]);
+        if (c.xirrev[r] && v < T(0)) v = T(0);
+        o.d += c.xsv[0][r] * (double)v;
+        o.f += c.xsv[1][r] * (double)v;
+      }
+      if (!liqn) o.d = o.f = 0.0;
+    }
+    return o;
+  };
+
   auto col_offsets = [&](int Xw, unsigned (&co)[3]) {
     int xm = Xw - 1, xp = Xw + 1;
     if (xm < 0) xm += nx;
@@ -870,6 +915,7 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
     if (hact) {
       const uint32_t fl = indom ? (flags_w(hw) | ((fluid && (double)m.rho[0] > thr) ? LF_LIQN : 0u)) : (uint32_t)TB_WALL;
       L.hpq[hs][hr] = PQ<T>{ps, q1, q2, flags_as<T>(fl)};
+      if (!EXPORT) L.hvs[hs][hr] = solid_dv((fl & LF_LIQN) != 0, hw, m);
       L.hr1[hs][hr] = m.rho[0];
       L.hr2[hs][hr] = m.rho[1];
 #pragma unroll
@@ -917,10 +963,22 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
     return TB_WALL;
   };
   uint32_t w_cur = 0, w_next = word_row(y0 - 1);
+  // The FP64 volume of this lane's node is loaded one iteration before its row
+  // is collided where it may be needed: at a reactive solid node, and at a
+  // fluid node next to a non-fluid one (a liquid node collects precipitate on
+  // its links to reactive solid).  A load in the middle of a row would wait for
+  // every memory operation the wavefront has in flight.
+  auto vol_pre = [](uint32_t w) -> bool {
+    const int t = (int)(w & TB_T);
+    return t == T_D || t == T_F || (t == T_FLUID && ((w >> NBF_SHIFT) & 0xFu) != 0xFu);
+  };
+  double v_cur = 0.0;
   int sm = 1, s0 = 2, sp = 0;
   for (int R = y0 - 2; R < y1; ++R) {
     const int Rn = R + 1;
     const uint32_t w_nn = word_row(R + 2);  // next iteration's row, loaded ahead
+    const bool vpre = !EXPORT && colown && Rn >= y0 && Rn < y1 && vol_pre(w_next);
+    const double v_nn = vpre ? A.V[(unsigned)Rn * upitch + (unsigned)X] : 0.0;
     T fn[2][9], gn[NSA][5];
     Mom<T, NS> mn;
     {
@@ -953,6 +1011,7 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
       const int cl = lane + 1;
       const uint32_t fl = indom ? (flags_w(w) | ((fluid && (double)mn.rho[0] > thr) ? LF_LIQN : 0u)) : (uint32_t)TB_WALL;
       L.pq[sp][cl] = PQ<T>{ps, q1, q2, flags_as<T>(fl)};
+      if (!EXPORT) L.vs[sp][cl] = solid_dv((fl & LF_LIQN) != 0, w, mn);
       L.r1[sp][cl] = mn.rho[0];
       L.r2[sp][cl] = mn.rho[1];
 #pragma unroll
@@ -971,6 +1030,7 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
         const int ce = lane ? SW + 1 : 0;
         const int hr = Rn - (y0 - 1);
         L.pq[sp][ce] = L.hpq[lane][hr];
+        if (!EXPORT) L.vs[sp][ce] = L.hvs[lane][hr];
         L.r1[sp][ce] = L.hr1[lane][hr];
         L.r2[sp][ce] = L.hr2[lane][hr];
 #pragma unroll
@@ -1061,17 +1121,6 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
           }
         }
       }
-      // concentration of a liquid D2Q5 neighbour as its own collision sees it
-      auto nbr_C = [&](int a, int kk) -> T {
-        const uint32_t v = nt[a];
-        const int nsf = sf_of(v);
-        if (nsf == SF_NONE || nsf == SF_SHARE) return T(0);  // liquid without content
-        T cn = T(0);
-#pragma unroll
-        for (int q = 0; q < NS; ++q)
-          if (q == kk) cn = L.C[q][slot(ey(a))][lane + 1 + ex(a)];
-        return cn;
-      };
 
       bool precip = false;
       bool storef = false, storeg = false;  // this lane holds valid post-collision populations
@@ -1335,40 +1384,51 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
 #pragma unroll
             for (int a = 1; a < 5; ++a) any_rs |= is_rsolid(nt[a]);
             if (any_rs) {
-              T phi[LBRX_MAX_RXN];
+              // every reaction's flux from this node's concentration, summed
+              // per reactive solid type into each species' net link flux (a
+              // product gains, a reactant loses it) and the precipitate
+              // volume one link collects
+              T dq[2][NSA];
+              double vq[2] = {0.0, 0.0};
+#pragma unroll
+              for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int kk = 0; kk < NSA; ++kk) dq[q][kk] = T(0);
               for (int r = 0; r < c.nhet; ++r) {
                 T v = k.xkap[r] * (sel<NS>(m.C, c.xre[r]) - k.xCeq[r]);
                 if (c.xirrev[r] && v < T(0)) v = T(0);
-                phi[r] = v;
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+#pragma unroll
+                  for (int kk = 0; kk < NS; ++kk) dq[q][kk] += k.xnu[q][r][kk] * v;
+                  vq[q] += c.xgv[q][r] * (double)v;
+                }
               }
-              double dv = 0.0;
-              bool touched = false;
+              // the links: the population heading into the solid comes back
+              // with the net flux of its species
+              int nlk[2] = {0, 0};
 #pragma unroll
               for (int a = 1; a < 5; ++a) {
-                if (!is_rsolid(nt[a])) continue;
-                const int tj = nt[a] & TB_T;
+                const bool rs = is_rsolid(nt[a]);
+                const bool sF = (nt[a] & TB_T) == T_F;
+                nlk[0] += rs && !sF ? 1 : 0;
+                nlk[1] += rs && sF ? 1 : 0;
 #pragma unroll
                 for (int kk = 0; kk < NS; ++kk) {
-                  for (int r = 0; r < c.nhet; ++r) {
-                    if (!(c.xsurf[r] & (1 << tj))) continue;
-                    if (c.xre[r] == kk) {
-                      g[kk][a] -= SFORM ? phi[r] * k.iJ1[kk] : phi[r];
-                      l_shet[kk] -= (double)phi[r];
-                    }
-                    if (c.xpr[r] == kk) {
-                      g[kk][a] += SFORM ? phi[r] * k.iJ1[kk] : phi[r];
-                      l_shet[kk] += (double)phi[r];
-                    }
-                  }
+                  const T d = sF ? dq[1][kk] : dq[0][kk];
+                  const T gv = g[kk][a] + (SFORM ? d * k.iJ1[kk] : d);
+                  g[kk][a] = rs ? gv : g[kk][a];
                 }
-                for (int r = 0; r < c.nhet; ++r)
-                  if ((c.xsurf[r] & (1 << tj)) && c.xmode[r] == HET_GROWS) {
-                    dv += c.xmvol[r] * (double)phi[r];
-                    touched = true;
-                  }
               }
+#pragma unroll
+              for (int kk = 0; kk < NS; ++kk)
+                l_shet[kk] += (double)nlk[0] * (double)dq[0][kk] + (double)nlk[1] * (double)dq[1][kk];
+              const double dv = (double)nlk[0] * vq[0] + (double)nlk[1] * vq[1];
+              const bool touched = (nlk[0] > 0 && c.xgrow[0]) || (nlk[1] > 0 && c.xgrow[1]);
               if (touched) {
-                const double Vn = A.V[idx] + dv;
+                // (a fluid node whose neighbour turned solid in the last step
+                // may not have its volume loaded ahead)
+                const double Vn = (vol_pre(w) ? v_cur : A.V[idx]) + dv;
                 A.V[idx] = Vn;
                 l_vdv += dv;
                 precip = Vn >= 1.0;  // the precipitate fills the node: SOLID_F next step
@@ -1394,23 +1454,17 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
           // fluxes on its D2Q5 links to liquid nodes, in direction then reaction order
           double dv = 0.0;
           bool touched = false;
-          if (NS > 0) {
+          const int q = t - T_D;
+          if (any_xsolid) {
 #pragma unroll
             for (int a = 1; a < 5; ++a) {
-              if (!is_liq(nt[a])) continue;
-              for (int r = 0; r < c.nhet; ++r) {
-                if (!(c.xsurf[r] & (1 << t))) continue;
-                const int md = c.xmode[r];
-                if (md != HET_CONSUMES && md != HET_MINERAL) continue;
-                T v = k.xkap[r] * (nbr_C(a, c.xre[r]) - k.xCeq[r]);
-                if (c.xirrev[r] && v < T(0)) v = T(0);
-                if (md == HET_CONSUMES) dv -= c.xmvol[r] * (double)v;
-                else dv += c.xmvol[r] * (double)v;
-                touched = true;
-              }
+              const bool lq = is_liq(nt[a]);
+              touched |= lq && (q ? c.xsolid[1] : c.xsolid[0]);
+              const VS nv = L.vs[slot(ey(a))][lane + 1 + ex(a)];
+              dv += lq ? (q ? nv.f : nv.d) : 0.0;
             }
           }
-          double Vn = A.V[idx];
+          double Vn = v_cur;  // (loaded ahead)
           if (touched) {
             Vn += dv;
             A.V[idx] = Vn;
@@ -1683,6 +1737,7 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
     mc = mn;
     w_cur = w_next;
     w_next = w_nn;
+    v_cur = v_nn;
     const int s_old = sm;
     sm = s0;
     s0 = sp;
@@ -2219,6 +2274,13 @@ void fill_kt(KT<T>& k, const lbrx_params* p, const KConst& c, const double* D) {
       if (c.hpr0[r] >= 0) k.hnu[r][c.hpr0[r]] += T(1);
       if (c.hpr1[r] >= 0) k.hnu[r][c.hpr1[r]] += T(1);
     }
+    for (int q = 0; q < 2; ++q) {
+      for (int sp = 0; sp < LBRX_MAX_SPECIES; ++sp) k.xnu[q][r][sp] = T(0);
+      if (r < c.nhet && (c.xsurf[r] & (1 << (T_D + q)))) {
+        k.xnu[q][r][c.xre[r]] -= T(1);
+        if (c.xpr[r] >= 0) k.xnu[q][r][c.xpr[r]] += T(1);
+      }
+    }
   }
   (void)D;
 }
@@ -2340,6 +2402,13 @@ lbrx_status lbrx_create(const lbrx_params* p, void* hip_stream, lbrx_ctx** out) 
     c.xkap[r] = (2.0 * Dk + h.k) > 0.0 ? 2.0 * Dk * h.k / (2.0 * Dk + h.k) : 0.0;
     c.xCeq[r] = h.C_eq;
     c.xmvol[r] = h.molar_volume;
+    for (int q = 0; q < 2; ++q) {
+      const bool on = (h.surface & (1u << (T_D + q))) != 0;
+      c.xgv[q][r] = on && h.mode == HET_GROWS ? h.molar_volume : 0.0;
+      c.xsv[q][r] = !on ? 0.0 : h.mode == HET_CONSUMES ? -h.molar_volume : h.mode == HET_MINERAL ? h.molar_volume : 0.0;
+      c.xgrow[q] |= on && h.mode == HET_GROWS;
+      c.xsolid[q] |= on && (h.mode == HET_CONSUMES || h.mode == HET_MINERAL);
+    }
   }
   fill_kt(x->kd, p, c, D);
   fill_kt(x->kf, p, c, D);
