@@ -421,6 +421,17 @@ template <typename T> __device__ inline T bload(__amdgpu_buffer_rsrc_t r, unsign
 // lines in the same launch, and keeping them out of the way leaves the L2 to
 // the rows the pulls of neighbouring rows read again.
 constexpr int STORE_NT = 2;
+// A buffer offset past the end of every array (each stays below it, checked
+// when a simulation is created).  Buffer accesses out of range read zero and
+// drop stores, so a lane with nothing to load or store still issues every
+// memory instruction with this offset: the wavefront's count of memory
+// operations is then the same on every path, and the compiler's waits for a
+// load do not also wait for loads and stores issued after it.
+constexpr unsigned OOB_OFF = 0xFFFFFF00u;
+__device__ inline unsigned gate(bool on, unsigned off) { return off | (on ? 0u : OOB_OFF); }
+// sel ? a : b on offsets, as integer arithmetic (a conditional expression
+// there can be compiled into a branch around each load)
+__device__ inline unsigned pick_off(bool sel, unsigned a, unsigned b) { return b + ((a - b) & (0u - (unsigned)sel)); }
 template <typename T> __device__ inline void bstore(T v, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
   if constexpr (sizeof(T) == 2) __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, (int)vo, (int)so, STORE_NT);
   else if constexpr (sizeof(T) == 4) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)vo, (int)so, STORE_NT);
@@ -605,6 +616,12 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
   const __amdgpu_buffer_rsrc_t rg = rsrc_of(A.g[cur], c.gbytes);
   const __amdgpu_buffer_rsrc_t rt = rsrc_of(A.t[cur], c.tbytes);
   const __amdgpu_buffer_rsrc_t rcw = rsrc_of(A.cw[cur], c.cbytes);
+  // written this step: the other buffer of each pair, and the volumes
+  const __amdgpu_buffer_rsrc_t wf_ = rsrc_of(A.f[1 - cur], c.fbytes);
+  const __amdgpu_buffer_rsrc_t wg_ = rsrc_of(A.g[1 - cur], c.gbytes);
+  const __amdgpu_buffer_rsrc_t wt_ = rsrc_of(A.t[1 - cur], c.tbytes);
+  const __amdgpu_buffer_rsrc_t wc_ = rsrc_of(A.cw[1 - cur], c.cbytes);
+  const __amdgpu_buffer_rsrc_t rv = rsrc_of(A.V, (unsigned)(c.plane * 8));
   const unsigned ncw = (unsigned)c.ncw;
 
   if (!EXPORT && lane < NRARE_SLOTS) L.rare[lane] = 0.0;
@@ -660,6 +677,7 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
     if constexpr (DEV) {
       T r1, r2;
       refs_of(w, r1, r2);
+      if (!validf) r1 = r2 = T(0);
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
         fb[0][q] = k.wc[q] * r1;
@@ -676,25 +694,18 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
         f[1][a] = q.hi;
       }
     };
-    // Zeroed before the branches, not in an else: stores to the same array
-    // on both sides of a branch get merged into one store through a pointer
-    // select, which sends the whole array to scratch memory.
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-      for (int a = 0; a < 9; ++a) f[s][a] = T(0);
-#pragma unroll
-    for (int kk = 0; kk < NSA; ++kk)
-#pragma unroll
-      for (int a = 0; a < 5; ++a) g[kk][a] = T(0);
-    if (validf) {
+    // Every lane issues every load; a node without flow populations (or
+    // solute) reads out of range, which gives zero.  16-bit storage: its
+    // references are taken as zero too, so that its populations stay zero.
+    {
       const unsigned own = co[1] + ur[1] * RSF;
-      fin(0, own);
+      fin(0, gate(validf, own));
 #pragma unroll
       for (int b = 1; b < 9; ++b) {
         const int a = opp(b);
         const bool src = (w >> (NBF_SHIFT + b - 1)) & 1u;
-        fin(a, src ? co[ex(b) + 1] + (ur[ey(b) + 1] * RSF + (unsigned)a * PS) : own + (unsigned)b * PS);
+        const unsigned nb = co[ex(b) + 1] + (ur[ey(b) + 1] * RSF + (unsigned)a * PS);
+        fin(a, gate(validf, pick_off(src, nb, own + (unsigned)b * PS)));
       }
       if constexpr (SFORM) {
         // Free outlet: the downward populations of the top row have two
@@ -703,31 +714,34 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
         if (outy && Yw >= ny - 2) {
           T r1, r2;
           refs_of(w, r1, r2);
+          if (!validf) r1 = r2 = T(0);
 #pragma unroll
           for (int b = 1; b < 9; ++b) {
             const int a = opp(b);
             const bool src = (w >> (NBF_SHIFT + b - 1)) & 1u;
             // the value read is slot a of the row above (pulled), or own slot b
             const bool zref = src ? (ey(a) < 0) : (ey(b) < 0 && Yw == ny - 1);
-            if (zref) {
-              f[0][a] -= r1;
-              f[1][a] -= r2;
-            }
+            f[0][a] -= zref ? r1 : T(0);
+            f[1][a] -= zref ? r2 : T(0);
           }
         }
       }
     }
-    if (NS > 0 && withg) {
+    if constexpr (NS == 0) {
+#pragma unroll
+      for (int a = 0; a < 5; ++a) g[0][a] = T(0);
+    } else {
       const unsigned own = (co[1] << GSH) + ur[1] * RSG;
       T gb[NSA][2];
       if constexpr (DEV) {
         // this node's solute reference codes, one word per four species
-        const unsigned cwo = (co[1] / PE) * 4u + ur[1] * ncw * upitch * 4u;
+        const unsigned cwo = gate(withg, (co[1] / PE) * 4u + ur[1] * ncw * upitch * 4u);
         const uint32_t cw0 = bload<uint32_t>(rcw, cwo, 0u);
         const uint32_t cw1 = NS > 4 ? bload<uint32_t>(rcw, cwo, upitch * 4u) : 0u;
 #pragma unroll
         for (int kk = 0; kk < NS; ++kk) {
-          const T cr = ref_value(((kk < 4 ? cw0 : cw1) >> (8 * (kk & 3))) & 255u, k.rbc[kk], SHC);
+          T cr = ref_value(((kk < 4 ? cw0 : cw1) >> (8 * (kk & 3))) & 255u, k.rbc[kk], SHC);
+          if (!withg) cr = T(0);
           gb[kk][0] = k.Jc[kk][0] * cr;
           gb[kk][1] = k.Jc[kk][1] * cr;
         }
@@ -746,7 +760,7 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
             if (j * SG + i < NS) g[j * SG + i][a] = gcv(j * SG + i, a, q.v[i]);
         }
       };
-      gin(0, own);
+      gin(0, gate(withg, own));
       // On the top row at a free outlet the ghost row above sends slot 2, not
       // slot 4, of the node itself: the writer keeps its post-collision
       // population 4 there (slot 4 may carry a reactive bounce-back).  The
@@ -758,7 +772,8 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
         const int a = opp(b);
         const bool src = (w >> (NBL_SHIFT + b - 1)) & 1u;
         const unsigned sh = (b == 2 && gtop) ? 2u * PSG : 0u;
-        gin(a, src ? (co[ex(b) + 1] << GSH) + (ur[ey(b) + 1] * RSG + (unsigned)a * PSG - sh) : own + (unsigned)b * PSG);
+        const unsigned nb = (co[ex(b) + 1] << GSH) + (ur[ey(b) + 1] * RSG + (unsigned)a * PSG - sh);
+        gin(a, gate(withg, pick_off(src, nb, own + (unsigned)b * PSG)));
       }
     }
   };
@@ -891,13 +906,32 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
     co[2] = (unsigned)xp * PE;
   };
 
+  // this lane's column
+  int Xw = x0 + lane;
+  const bool colin = wrap(Xw, nx, c.per_x);
+  const int X = x0 + lane;
+  const bool colown = X < nx;
+  unsigned co[3];
+  col_offsets(colin ? Xw : 0, co);
+
+  // status word of this lane's column in row Y (the column is wrapped once)
+  auto word_row = [&](int Y) -> uint32_t {
+    const bool in = colin && wrap_y(Y);
+    const uint32_t v = bload<uint32_t>(rt, gate(in, (unsigned)Xw * 4u + (unsigned)Y * upitch * 4u), 0u);
+    return in ? v : (uint32_t)TB_WALL;
+  };
+  uint32_t w_cur = 0, w_next = word_row(y0 - 1);
+  // (loaded before the halo columns, so that the loads there separate it from
+  // its first use)
+
   // ------------------------------------------------------------ halo columns
   {
     const int hs = lane >> 5, hr = lane & 31;
     const bool hact = hr < nrow + 2;
     int HX = hs ? x0 + SW : x0 - 1, HY = y0 - 1 + hr;
     const bool indom = hact && wrap(HX, nx, c.per_x) && wrap_y(HY);
-    const uint32_t hw = indom ? bload<uint32_t>(rt, (unsigned)HX * 4u, (unsigned)HY * upitch * 4u) : (uint32_t)TB_WALL;
+    const uint32_t hwl = bload<uint32_t>(rt, gate(indom, (unsigned)HX * 4u + (unsigned)HY * upitch * 4u), 0u);
+    const uint32_t hw = indom ? hwl : (uint32_t)TB_WALL;
     const int t = (int)(hw & TB_T);
     const bool fluid = indom && t == T_FLUID;
     const bool validf = indom && (t == T_FLUID || (hw & TB_STR));
@@ -933,14 +967,6 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
     }
   }
 
-  // this lane's column
-  int Xw = x0 + lane;
-  const bool colin = wrap(Xw, nx, c.per_x);
-  const int X = x0 + lane;
-  const bool colown = X < nx;
-  unsigned co[3];
-  col_offsets(colin ? Xw : 0, co);
-
   // per-lane balance contributions over the item's rows, in FP64: the gas
   // component's homogeneous source (the liquid component's is its exact
   // negative), the solute sources and the heterogeneous exchange
@@ -957,12 +983,6 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
   // The first two iterations (R = y0 - 2, y0 - 1) only fill the ring.
   T fc[2][9], gc[NSA][5];
   Mom<T, NS> mc;
-  // status word of this lane's column in row Y (the column is wrapped once)
-  auto word_row = [&](int Y) -> uint32_t {
-    if (colin && wrap_y(Y)) return bload<uint32_t>(rt, (unsigned)Xw * 4u, (unsigned)Y * upitch * 4u);
-    return TB_WALL;
-  };
-  uint32_t w_cur = 0, w_next = word_row(y0 - 1);
   // The FP64 volume of this lane's node is loaded one iteration before its row
   // is collided where it may be needed: at a reactive solid node, and at a
   // fluid node next to a non-fluid one (a liquid node collects precipitate on
@@ -978,7 +998,7 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
     const int Rn = R + 1;
     const uint32_t w_nn = word_row(R + 2);  // next iteration's row, loaded ahead
     const bool vpre = !EXPORT && colown && Rn >= y0 && Rn < y1 && vol_pre(w_next);
-    const double v_nn = vpre ? A.V[(unsigned)Rn * upitch + (unsigned)X] : 0.0;
+    const double v_nn = EXPORT ? 0.0 : bload<double>(rv, gate(vpre, ((unsigned)Rn * upitch + (unsigned)X) * 8u), 0u);
     T fn[2][9], gn[NSA][5];
     Mom<T, NS> mn;
     {
@@ -1046,6 +1066,10 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 
+    // what row R stores, and where (out of range: nothing)
+    unsigned so_f = OOB_OFF, so_g = OOB_OFF, so_t = OOB_OFF, so_c = OOB_OFF, so_v = OOB_OFF;
+    uint32_t wst = 0u, cws0 = 0u, cws1 = 0u;
+    double vnew = 0.0;
     if (R >= y0) {
       // ---------------------------------------------------- phase 2, row R
       const uint32_t w = w_cur;
@@ -1429,7 +1453,8 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
                 // (a fluid node whose neighbour turned solid in the last step
                 // may not have its volume loaded ahead)
                 const double Vn = (vol_pre(w) ? v_cur : A.V[idx]) + dv;
-                A.V[idx] = Vn;
+                vnew = Vn;
+                so_v = idx * 8u;
                 l_vdv += dv;
                 precip = Vn >= 1.0;  // the precipitate fills the node: SOLID_F next step
               }
@@ -1467,7 +1492,8 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
           double Vn = v_cur;  // (loaded ahead)
           if (touched) {
             Vn += dv;
-            A.V[idx] = Vn;
+            vnew = Vn;
+            so_v = idx * 8u;
             l_vdv += dv;
           }
           if (Vn <= 0.0) {
@@ -1501,7 +1527,8 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
               r_v[0] = (double)rb0;
               r_v[1] = (double)rb1;
               r_v[4] = Vn;
-              A.V[idx] = 0.0;
+              vnew = 0.0;
+              so_v = idx * 8u;
               tnew = T_FLUID;
             }
           }
@@ -1609,14 +1636,15 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
       } else {
         // -------------------------------------------------- own-slot stores
         // Every lane writes its node's slots at the unwrapped column (a lane
-        // past nx writes into the row padding).  A 32-lane group writes all its
-        // lanes when any of them holds valid populations, so that lines are
-        // written whole; a lane without valid populations writes values nobody
-        // reads (its slots are not pulled from next step).
-        const __amdgpu_buffer_rsrc_t wf_ = rsrc_of(A.f[1 - cur], c.fbytes);
-        const __amdgpu_buffer_rsrc_t wg_ = rsrc_of(A.g[1 - cur], c.gbytes);
-        const __amdgpu_buffer_rsrc_t wt_ = rsrc_of(A.t[1 - cur], c.tbytes);
-        bstore<uint32_t>(wout, wt_, (unsigned)X * 4u, (unsigned)R * upitch * 4u);
+        // past nx writes into the row padding).  A group of lanes that share a
+        // 128-byte line writes all its lanes when any of them holds valid
+        // populations, so that lines are written whole; a lane without valid
+        // populations writes values nobody reads (its slots are not pulled from
+        // next step).  Here the values are put in the form they are stored in
+        // and the offsets set; the stores follow the row (every lane, every
+        // iteration, out of range where nothing is stored).
+        so_t = (unsigned)X * 4u + (unsigned)R * upitch * 4u;
+        wst = wout;
         const unsigned long long bf = __ballot(storef);
         const unsigned long long bg = __ballot(storeg);
         // a 128-byte line holds the flow slots of 128 / PE lanes (32 for
@@ -1631,52 +1659,47 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
         const bool gg = ((bg >> (lane & ~(GG - 1))) & GGM) != 0ull;
         const bool gw = ((bg >> (lane & 32)) & 0xffffffffull) != 0ull;
         const unsigned xo = (unsigned)X * PE;
-        if (gf) {
-          const unsigned vo = xo + (unsigned)R * RSF;
-          if constexpr (REFS) {
-            // deviation from w_a x the reference of the node that pulls the
-            // population next step: the neighbour it heads to if that one is
-            // fluid now, else this node (bounce-back; a dissolved node reads
-            // all its slots back)
-            RF<T> ro;
-            if (dissolved) {
-              ro.r1 = ref_value(ref_code(rdis[0], k.rb1, SH1, MAX1), k.rb1, SH1);
-              ro.r2 = ref_value(ref_code(rdis[1], k.rb2, SH2, MAX2), k.rb2, SH2);
-            } else {
-              ro = L.rf[s0][lane + 1];
-            }
-            if constexpr (DEV) {
+        so_f = gate(gf, xo + (unsigned)R * RSF);
+        if constexpr (REFS) {
+          // deviation from w_a x the reference of the node that pulls the
+          // population next step: the neighbour it heads to if that one is
+          // fluid now, else this node (bounce-back; a dissolved node reads
+          // all its slots back)
+          RF<T> ro;
+          if (dissolved) {
+            ro.r1 = ref_value(ref_code(rdis[0], k.rb1, SH1, MAX1), k.rb1, SH1);
+            ro.r2 = ref_value(ref_code(rdis[1], k.rb2, SH2, MAX2), k.rb2, SH2);
+          } else {
+            ro = L.rf[s0][lane + 1];
+          }
+          if constexpr (DEV) {
 #pragma unroll
-              for (int a = 0; a < 9; ++a) {
-                RF<T> rd = ro;
-                if (a != 0 && !dissolved && is_fluid(nt[a])) rd = L.rf[slot(ey(a))][lane + 1 + ex(a)];
-                bstore2<ST>(dev_out<SM>(__builtin_fmaf(f[0][a], k.sc[0], -(k.wsc[0][wcls(a)] * rd.r1))),
-                            dev_out<SM>(__builtin_fmaf(f[1][a], k.sc[1], -(k.wsc[1][wcls(a)] * rd.r2))), wf_, vo,
-                            (unsigned)a * PS);
-              }
-            } else {
-              // FP32: s_a is a deviation from the decoding reference of this
-              // step (zero for a dissolved node, which holds rest populations
-              // w_a rho); re-referenced to the reader's, an exact difference of
-              // two coded values.  The top row's downward populations at a free
-              // outlet keep reference zero (they have two readers).
-              T o1 = T(0), o2 = T(0);
-              if (!dissolved) refs_of(w, o1, o2);
-#pragma unroll
-              for (int a = 0; a < 9; ++a) {
-                RF<T> rd = ro;
-                if (a != 0 && !dissolved && is_fluid(nt[a])) rd = L.rf[slot(ey(a))][lane + 1 + ex(a)];
-                if (top_out && ey(a) < 0) rd = RF<T>{T(0), T(0)};
-                bstore2<ST>(f[0][a] + (o1 - rd.r1), f[1][a] + (o2 - rd.r2), wf_, vo, (unsigned)a * PS);
-              }
+            for (int a = 0; a < 9; ++a) {
+              RF<T> rd = ro;
+              if (a != 0 && !dissolved && is_fluid(nt[a])) rd = L.rf[slot(ey(a))][lane + 1 + ex(a)];
+              f[0][a] = __builtin_fmaf(f[0][a], k.sc[0], -(k.wsc[0][wcls(a)] * rd.r1));
+              f[1][a] = __builtin_fmaf(f[1][a], k.sc[1], -(k.wsc[1][wcls(a)] * rd.r2));
             }
           } else {
+            // FP32: s_a is a deviation from the decoding reference of this
+            // step (zero for a dissolved node, which holds rest populations
+            // w_a rho); re-referenced to the reader's, an exact difference of
+            // two coded values.  The top row's downward populations at a free
+            // outlet keep reference zero (they have two readers).
+            T o1 = T(0), o2 = T(0);
+            if (!dissolved) refs_of(w, o1, o2);
 #pragma unroll
-            for (int a = 0; a < 9; ++a) bstore2<ST>(f[0][a], f[1][a], wf_, vo, (unsigned)a * PS);
+            for (int a = 0; a < 9; ++a) {
+              RF<T> rd = ro;
+              if (a != 0 && !dissolved && is_fluid(nt[a])) rd = L.rf[slot(ey(a))][lane + 1 + ex(a)];
+              if (top_out && ey(a) < 0) rd = RF<T>{T(0), T(0)};
+              f[0][a] += o1 - rd.r1;
+              f[1][a] += o2 - rd.r2;
+            }
           }
         }
-        if (NS > 0 && gg) {
-          const unsigned vo = (xo << GSH) + (unsigned)R * RSG;
+        if constexpr (NS > 0) {
+          so_g = gate(gg, (xo << GSH) + (unsigned)R * RSG);
           if constexpr (DEV) {
             // deviation from J_a x the reference concentration of the reader:
             // the liquid neighbour it heads to, else this node
@@ -1688,41 +1711,45 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
             for (int a = 0; a < 5; ++a) {
               const bool nbr = a != 0 && !donor && is_liq(nt[a]);
 #pragma unroll
-              for (int j = 0; j < NGR; ++j) {
-                Grp<ST, SG> hv;
-#pragma unroll
-                for (int i = 0; i < SG; ++i) {
-                  const int kk = j * SG + i;
-                  if (kk < NS) {
-                    const T cr = nbr ? L.Cf[kk][slot(ey(a))][lane + 1 + ex(a)] : co_[kk];
-                    hv.v[i] = dev_out<SM>(__builtin_fmaf(g[kk][a], k.scg[kk], -(k.Jsc[kk][a == 0 ? 0 : 1] * cr)));
-                  } else {
-                    hv.v[i] = 0;
-                  }
-                }
-                bstoreg<ST, SG>(hv, wg_, vo, (unsigned)(j * 5 + a) * PSG);
+              for (int kk = 0; kk < NS; ++kk) {
+                const T cr = nbr ? L.Cf[kk][slot(ey(a))][lane + 1 + ex(a)] : co_[kk];
+                g[kk][a] = __builtin_fmaf(g[kk][a], k.scg[kk], -(k.Jsc[kk][a == 0 ? 0 : 1] * cr));
               }
             }
             // the node's solute reference codes, for its own pull next step
-            const __amdgpu_buffer_rsrc_t wc_ = rsrc_of(A.cw[1 - cur], c.cbytes);
-            const unsigned cvo = (unsigned)X * 4u + (unsigned)R * ncw * upitch * 4u;
-            if (gw) {
-              bstore<uint32_t>(cwc0, wc_, cvo, 0u);
-              if (NS > 4) bstore<uint32_t>(cwc1, wc_, cvo, upitch * 4u);
-            }
-          } else {
-#pragma unroll
-            for (int j = 0; j < NGR; ++j)
-#pragma unroll
-              for (int a = 0; a < 5; ++a) {
-                Grp<ST, SG> q;
-#pragma unroll
-                for (int i = 0; i < SG; ++i) q.v[i] = j * SG + i < NS ? g[j * SG + i][a] : T(0);
-                bstoreg<ST, SG>(q, wg_, vo, (unsigned)(j * 5 + a) * PSG);
-              }
+            so_c = gate(gw, (unsigned)X * 4u + (unsigned)R * ncw * upitch * 4u);
+            cws0 = cwc0;
+            cws1 = cwc1;
           }
         }
       }
+    }
+
+    if constexpr (!EXPORT) {
+      // the stores of row R (out of range in the two ring-filling iterations)
+      auto cvt = [](T v) -> ST {
+        if constexpr (DEV) return dev_out<SM>(v);
+        else return v;
+      };
+      bstore<uint32_t>(wst, wt_, so_t, 0u);
+#pragma unroll
+      for (int a = 0; a < 9; ++a) bstore2<ST>(cvt(fc[0][a]), cvt(fc[1][a]), wf_, so_f, (unsigned)a * PS);
+      if constexpr (NS > 0) {
+#pragma unroll
+        for (int j = 0; j < NGR; ++j)
+#pragma unroll
+          for (int a = 0; a < 5; ++a) {
+            Grp<ST, SG> q;
+#pragma unroll
+            for (int i = 0; i < SG; ++i) q.v[i] = j * SG + i < NS ? cvt(gc[j * SG + i][a]) : ST(0);
+            bstoreg<ST, SG>(q, wg_, so_g, (unsigned)(j * 5 + a) * PSG);
+          }
+        if constexpr (DEV) {
+          bstore<uint32_t>(cws0, wc_, so_c, 0u);
+          if (NS > 4) bstore<uint32_t>(cws1, wc_, so_c, upitch * 4u);
+        }
+      }
+      bstore<double>(vnew, rv, so_v, 0u);
     }
 
     // next row
@@ -1970,7 +1997,7 @@ std::string validate(const lbrx_params* p) {
     const unsigned long long sg = (unsigned long long)species_group(p->n_species, (int)esz);
     const unsigned long long ge = 5ull * ((p->n_species + sg - 1) / sg) * sg;
     const unsigned long long np = 18ull > ge ? 18ull : ge;
-    if (np * pitch * (unsigned long long)p->ny * esz >= (1ull << 32))
+    if (np * pitch * (unsigned long long)p->ny * esz >= (unsigned long long)OOB_OFF)
       return "lattice too large: a population array must stay below 4 GiB (use FP32 or fewer species)";
   }
   if (ns > 0 && !p->C0) return "C0 is required when n_species > 0";
