@@ -82,24 +82,35 @@ def measured_traffic(precision, n):
     return rec["traffic_bytes_per_launch"]
 
 
-def serving(n, interarrival):
+def serving(n, interarrival, steps=(200, 2000), cap_gb=200.0, mode="both", progress=30.0):
     """Poisson arrivals of many-simulation requests (square porous lattices of
-    side 64-1024, 200-2000 steps, FP32 or FP16-deviation storage), served by
-    the batched loop and, for comparison, one at a time with plain FP32 runs."""
+    side 64-1024, step counts log-uniform in `steps`, FP32 or FP16-deviation
+    storage drawn per request), served by the batched loop (admission capped at
+    `cap_gb` of device memory) and, for comparison, the same requests one at a
+    time with plain FP32 runs.  `mode` runs both sides, or only one ("batched",
+    "plain"): the same seed gives the same requests, so a long stream can be
+    measured in two runs."""
     from paper_1410_3464_amd import serve
 
-    reqs = serve.poisson_requests(n, interarrival, seed=11)
-    batched = serve.Server(tick=60).run(reqs)
-    plain = serve.run_plain(serve.clone_requests(reqs), precision="f32")
-    print(f"# serving batched {batched} plain {plain}", file=sys.stderr, flush=True)
-    return {
-        "workload": f"{n} requests, Poisson arrivals every {interarrival * 1e3:.0f} ms on average, "
-                    "porous lattices 64^2-1024^2, 200-2000 steps, f32 or f16dev; plain: one at a time in f32",
-        "batched": batched, "plain": plain,
-        "p50_speedup": round(plain["p50_ms"] / batched["p50_ms"], 2),
-        "p99_speedup": round(plain["p99_ms"] / batched["p99_ms"], 2),
-        "mlups_ratio": round(batched["mlups"] / plain["mlups"], 2),
-    }
+    reqs = serve.poisson_requests(n, interarrival, seed=11, steps=steps, lazy=True)
+    out = {"workload": f"{n} requests, Poisson arrivals every {interarrival * 1e3:.0f} ms on average "
+                       f"(over {reqs[-1].arrival:.0f} s), porous lattices 64^2-1024^2, {steps[0]}-{steps[1]} steps, "
+                       f"f32 or f16dev, admission cap {cap_gb:g} GB; plain: one at a time in f32"}
+    if mode in ("both", "batched"):
+        out["batched"] = serve.Server(tick=60, hbm_cap=cap_gb * 1e9, progress=progress).run(reqs)
+        print(f"# serving batched {out['batched']}", file=sys.stderr, flush=True)
+    if mode in ("both", "plain"):
+        out["plain"] = serve.run_plain(serve.clone_requests(reqs), precision="f32", progress=progress)
+        print(f"# serving plain {out['plain']}", file=sys.stderr, flush=True)
+    span = reqs[-1].arrival
+    if span < 600 or steps != (1000, 50000) or cap_gb != 200.0:
+        out["note"] = ("a short stand-in for the 10-minute stream of 1000-50000-step requests under a 200 GB cap "
+                       "(bench.py --serve-requests 600 --serve-interarrival-ms 1000 --serve-steps 1000,50000 runs it)")
+    if mode == "both":
+        out["p50_speedup"] = round(out["plain"]["p50_ms"] / out["batched"]["p50_ms"], 2)
+        out["p99_speedup"] = round(out["plain"]["p99_ms"] / out["batched"]["p99_ms"], 2)
+        out["mlups_ratio"] = round(out["batched"]["mlups"] / out["plain"]["mlups"], 2)
+    return out
 
 
 def batched(n_inst, steps, warmup=30, plain_warmup=30):
@@ -136,7 +147,11 @@ def batched(n_inst, steps, warmup=30, plain_warmup=30):
     print(f"# batched: {n_inst} instances, {nodes} nodes, {wall_b / steps * 1e3:.3f} ms per step",
           file=sys.stderr, flush=True)
     wall_p = 0.0
-    for p in probs:
+    t_last = time.perf_counter()
+    for i, p in enumerate(probs):
+        if time.perf_counter() - t_last > 30:
+            t_last = time.perf_counter()
+            print(f"# one at a time: {i}/{n_inst} instances done", file=sys.stderr, flush=True)
         s = Lbrx(p, "f32", stream=st.cuda_stream)
         s.step(plain_warmup)
         st.synchronize()
@@ -157,6 +172,9 @@ def batched(n_inst, steps, warmup=30, plain_warmup=30):
         "batched_ms_per_step": round(wall_b / steps * 1e3, 3),
         "one_at_a_time_s": round(wall_p, 3),
         "seg_rows_by_size_class": {f"{k[0]}": v for k, v in table().items() if k[1] == "f32" and k[3] == "batch"},
+        **({} if (n_inst, steps) == (256, 5000) else
+           {"note": "a shorter stand-in for 256 instances x 5000 steps (bench.py --batch-instances 256 "
+                    "--batch-steps 5000 runs it)"}),
     }
 
 
@@ -195,19 +213,42 @@ def precision_comparison(prob, precision, main_mlups, steps, warmup):
             else round(measured_traffic(precision, prob.nx) / 1e9, 4)}
 
 
-def cpu_baseline(prob, steps):
-    """The FP64 oracle, as it stands, single-threaded on the host: `steps` steps of
-    the same lattice."""
+def cpu_info():
+    """The host's CPU model, logical CPU count and the CPUs this process may use."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return model, os.cpu_count() or 1, avail
+
+
+def cpu_baseline(prob, steps, threads=1):
+    """The FP64 oracle, as it stands, on the host: `steps` steps of `prob` after
+    one untimed step, on `threads` threads (its node loops run in parallel, its
+    balances serially in node order: the result is the single-thread one)."""
     from oracle import OracleSim, build_oracle
 
     build_oracle()
-    s = OracleSim(prob)
+    s = OracleSim(prob, threads=threads)
     s.step(1)  # first touch of the arrays
     t0 = time.perf_counter()
     s.step(steps)
     dt = time.perf_counter() - t0
     s.close()
     return prob.nx * prob.ny * steps / dt / 1e6, dt
+
+
+def cpu_threads():
+    """Threads for the all-core oracle run: OMP_NUM_THREADS if set, else the
+    CPUs this process may use."""
+    _, _, avail = cpu_info()
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    return max(1, min(int(env), avail) if env.isdigit() and int(env) > 0 else avail)
 
 
 def main():
@@ -219,9 +260,16 @@ def main():
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="also time the oracle on the 1024x512 porous medium (200 steps) and the 4096^2 one "
+                         "(10 steps), single-threaded and on all cores")
     ap.add_argument("--serve-requests", type=int, default=48,
                     help="requests of the serving comparison (0: skip it)")
     ap.add_argument("--serve-interarrival-ms", type=float, default=15.0)
+    ap.add_argument("--serve-steps", default="200,2000", help="step-count range of the requests")
+    ap.add_argument("--serve-cap-gb", type=float, default=200.0)
+    ap.add_argument("--serve-mode", default="both", choices=["both", "batched", "plain"])
+
     ap.add_argument("--batch-instances", type=int, default=256,
                     help="instances of the many-simulations comparison (0: skip it)")
     ap.add_argument("--batch-steps", type=int, default=200)
@@ -334,14 +382,31 @@ def main():
     if args.batch_instances > 0:
         out["batched"] = batched(args.batch_instances, args.batch_steps)
     if args.serve_requests > 0:
-        out["serving"] = serving(args.serve_requests, args.serve_interarrival_ms / 1e3)
+        lo, hi = (int(v) for v in args.serve_steps.split(","))
+        out["serving"] = serving(args.serve_requests, args.serve_interarrival_ms / 1e3, steps=(lo, hi),
+                                 cap_gb=args.serve_cap_gb, mode=args.serve_mode)
     if not args.no_cpu:
-        cpu_mlups, dt = cpu_baseline(prob, args.cpu_steps)
+        model, nproc, avail = cpu_info()
+        nt = cpu_threads()
+        m1, dt1 = cpu_baseline(prob, args.cpu_steps, 1)
+        mt, dtt = cpu_baseline(prob, args.cpu_steps, nt)
         out["cpu_baseline"] = {
-            "value": round(cpu_mlups, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"{args.cpu_steps} FP64 oracle steps of the same {prob.nx}x{prob.ny} lattice "
-                      f"after one untimed step ({dt:.1f}s)",
+            "value": round(mt, 3), "unit": "MLUPS", "cores": nt, "kind": "oracle",
+            "sample": f"{args.cpu_steps} FP64 oracle steps of the same {prob.nx}x{prob.ny} lattice after one "
+                      f"untimed step, node loops on {nt} threads ({dtt:.1f}s)",
+            "single_thread": {"value": round(m1, 3), "unit": "MLUPS", "cores": 1, "seconds": round(dt1, 2)},
+            "cpu_model": model, "nproc": nproc, "cpus_available": avail,
         }
+        if args.cpu_full:
+            from paper_1410_3464_amd import workloads as W
+            full = {}
+            for tag, p, n in (("porous-1024x512", W.config1(), 200), (prob.name, prob, 10)):
+                a1, s1 = cpu_baseline(p, n, 1)
+                an, sn = cpu_baseline(p, n, nt)
+                full[tag] = {"steps": n, "single_thread_mlups": round(a1, 3), "single_thread_s": round(s1, 2),
+                             "threads": nt, "threaded_mlups": round(an, 3), "threaded_s": round(sn, 2)}
+                print(f"# cpu {tag}: {full[tag]}", file=sys.stderr, flush=True)
+            out["cpu_baseline"]["full"] = full
     print(json.dumps(out), flush=True)
 
 

@@ -107,7 +107,7 @@ typedef struct {
 
 typedef struct {
   uint32_t abi_version;  /* must be LBRX_ABI_VERSION */
-  int32_t nx, ny;        /* lattice size, each >= 3 */
+  int32_t nx, ny;        /* lattice size, each >= 1 */
   uint32_t periodic;     /* bit 0: x periodic, bit 1: y periodic; a non-periodic
                             side is a halfway bounce-back wall just outside the domain,
                             except that bit 2 makes the side beyond y = ny - 1 a free
@@ -170,7 +170,8 @@ typedef struct {
   double mass_rem[2];   /* displaced mass that found no fluid neighbour */
   double sol_src[LBRX_MAX_SPECIES]; /* homogeneous solute sources (Eq. 28) */
   double sol_het[LBRX_MAX_SPECIES]; /* net surface exchange (Eq. 29-31) */
-  double sol_rem[LBRX_MAX_SPECIES]; /* solute of nodes leaving the liquid with no liquid neighbour */
+  double sol_rem[LBRX_MAX_SPECIES]; /* solute dropped: always 0 (a node leaving the liquid passes its
+                                       content to its liquid D2Q5 neighbours, or keeps it at rest) */
   double vol_dv;        /* all volume-of-pixel increments (Eq. 33, 35) */
   double vol_clip;      /* sum of the non-positive volumes of removed solid nodes */
   double n_psi_clamp;   /* negative psi arguments clamped to zero */
@@ -178,11 +179,16 @@ typedef struct {
   double steps;
 } lbrx_ledger;
 
-/* Host output buffers of nx*ny (C: n_species*nx*ny) for lbrx_fields; any may
- * be NULL.  Values describe the state after the steps taken so far:
- * rho at nodes carrying flow populations, u the physical velocity of Eq. 19 at
- * fluid nodes, C at nodes carrying solute, V solid / precipitate volume,
- * type the node type, liquid the liquid mark of the next step. */
+/* Host output buffers of nx*ny (C: n_species*nx*ny) for lbrx_fields.  The
+ * fields wanted are selected by the non-NULL pointers: any may be NULL, and a
+ * call that asks for none of rho1, rho2, ux, uy, C and liquid runs no read-out
+ * kernel.  Values describe the state after the steps taken so far, as the
+ * next step starts from it (its populations streamed): rho at nodes carrying
+ * flow populations, u the physical velocity of Eq. 19 at fluid nodes, C the
+ * solute each node holds once the shares in transit from nodes that left the
+ * liquid are delivered (Sec. 4.5), V solid / precipitate volume, type the node
+ * type, liquid the liquid mark the next step takes (rho1 above liquid_frac
+ * times the last step's maximum, Sec. 4.5). */
 typedef struct {
   double* rho1;
   double* rho2;

@@ -2737,11 +2737,17 @@ lbrx_status fields_into(lbrx_ctx* x, lbrx_fields_out* o, double* stage) {
   const KConst& c = x->c;
   const size_t plane = (size_t)c.plane;
   double* const ledsum = stage + (5 + (size_t)c.ns) * plane;
-  HIPCHK(x, hipMemsetAsync(stage, 0, (5 + (size_t)c.ns) * plane * 8, x->stream));
-  launch_one(x, true, stage);
-  HIPCHK(x, hipGetLastError());
-  hipLaunchKernelGGL(k_ledger_sum, dim3(NLED), dim3(LSUM_THREADS), 0, x->stream, x->led, c.nitems, ledsum);
-  HIPCHK(x, hipGetLastError());
+  // the read-out kernel runs only for the fields it forms
+  const bool moments = o->rho1 || o->rho2 || o->ux || o->uy || (o->C && c.ns > 0) || o->liquid;
+  if (moments) {
+    HIPCHK(x, hipMemsetAsync(stage, 0, (5 + (size_t)c.ns) * plane * 8, x->stream));
+    launch_one(x, true, stage);
+    HIPCHK(x, hipGetLastError());
+  }
+  if (o->ledger) {
+    hipLaunchKernelGGL(k_ledger_sum, dim3(NLED), dim3(LSUM_THREADS), 0, x->stream, x->led, c.nitems, ledsum);
+    HIPCHK(x, hipGetLastError());
+  }
   HIPCHK(x, hipStreamSynchronize(x->stream));
   const size_t sp = (size_t)c.pitch * 8, dp = (size_t)c.nx * 8;
   auto get2d = [&](double* dst, const double* src) -> hipError_t {

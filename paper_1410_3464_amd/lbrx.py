@@ -268,24 +268,27 @@ class Lbrx:
     def stream(self):
         return self._lib.lbrx_stream(self._h)
 
-    def fields(self, noalloc=False):
-        """The fields in FP64 (lbrx_fields; lbrx_fields_noalloc with noalloc=True)."""
+    def fields(self, noalloc=False, only=None):
+        """The fields in FP64 (lbrx_fields; lbrx_fields_noalloc with noalloc=True).
+        `only`: names of the fields wanted (rho1, rho2, ux, uy, C, V, type,
+        liquid, ledger, rho_max_prev); the others are not read out."""
         N, ny, nx, ns = self.nx * self.ny, self.ny, self.nx, self.ns
+        want = (lambda k: True) if only is None else (lambda k: k in only)
         r1, r2, ux, uy, V = (np.zeros(N) for _ in range(5))
         Cc = np.zeros(max(ns, 1) * N)
         t = np.zeros(N, np.uint8)
         lq = np.zeros(N, np.uint8)
         led = np.zeros(LEDGER_LEN)
         rmax = np.zeros(1)
-        o = FieldsOut(_ptr(r1), _ptr(r2), _ptr(ux), _ptr(uy), _ptr(Cc), _ptr(V), _ptr(t), _ptr(lq),
-                      _ptr(led), _ptr(rmax))
+        arrs = dict(rho1=r1, rho2=r2, ux=ux, uy=uy, C=Cc, V=V, type=t, liquid=lq, ledger=led, rho_max_prev=rmax)
+        o = FieldsOut(*(_ptr(a) if want(k) else None for k, a in arrs.items()))
         fn = self._lib.lbrx_fields_noalloc if noalloc else self._lib.lbrx_fields
         self._check(fn(self._h, C.byref(o)))
         out = dict(rho1=r1.reshape(ny, nx), rho2=r2.reshape(ny, nx), ux=ux.reshape(ny, nx),
                    uy=uy.reshape(ny, nx), C=Cc[: ns * N].reshape(ns, ny, nx), type=t.reshape(ny, nx),
                    liquid=lq.reshape(ny, nx), V=V.reshape(ny, nx), rho_max_prev=float(rmax[0]))
         out["ledger"] = unpack_ledger(led)
-        return out
+        return {k: v for k, v in out.items() if want(k)}
 
     def save_state(self):
         """The whole simulation state (lbrx_save_state) as a uint8 array."""

@@ -19,6 +19,7 @@ from __future__ import annotations
 import collections
 import dataclasses
 import math
+import sys
 import time
 
 import numpy as np
@@ -32,7 +33,7 @@ ESZ = {"f64": 8, "f32": 4, "f16dev": 2, "bf16dev": 2}
 @dataclasses.dataclass
 class Request:
     rid: int
-    prob: object
+    prob: object  # the problem, or None: generated from `spec` when admitted
     steps: int
     precision: str
     arrival: float  # seconds after the start of the run
@@ -40,21 +41,38 @@ class Request:
     finish: float = math.nan
     status: str = "pending"
     fields: dict | None = None
+    spec: tuple | None = None  # (seed, smin, smax) of a batch_instance made on admission
+    side: int = 0
 
     @property
     def latency(self):
         return self.finish - self.arrival
 
     @property
+    def dims(self):
+        """(nx, ny, species) without generating the problem."""
+        if self.prob is not None:
+            return self.prob.nx, self.prob.ny, self.prob.n_species
+        return self.side, self.side, 4
+
+    @property
     def updates(self):
-        return self.prob.nx * self.prob.ny * self.steps
+        nx, ny, _ = self.dims
+        return nx * ny * self.steps
+
+    def problem(self):
+        """The problem (generated now for a request that carries only its spec;
+        not kept, so that a long stream of requests holds no host arrays)."""
+        return self.prob if self.prob is not None else W.batch_instance(*self.spec)
 
 
 def poisson_requests(n, mean_interarrival, seed=0, steps=(200, 2000), sizes=(64, 1024),
-                     precisions=("f32", "f16dev")):
+                     precisions=("f32", "f16dev"), lazy=False):
     """n requests with exponential inter-arrival times: lattice instances of the
     many-simulations workload (sides log-uniform in `sizes`), step counts
-    log-uniform in `steps`, precision drawn uniformly from `precisions`."""
+    log-uniform in `steps`, precision drawn uniformly from `precisions`.  With
+    `lazy`, a request carries only the seed of its instance, generated when it
+    is admitted."""
     rng = np.random.default_rng(seed)
     t = np.cumsum(rng.exponential(mean_interarrival, size=n))
     t -= t[0]
@@ -62,31 +80,46 @@ def poisson_requests(n, mean_interarrival, seed=0, steps=(200, 2000), sizes=(64,
     for i in range(n):
         nsteps = int(round(math.exp(rng.uniform(math.log(steps[0]), math.log(steps[1])))))
         prec = precisions[int(rng.integers(len(precisions)))]
-        prob = W.batch_instance(seed * 100_000 + i, smin=sizes[0], smax=sizes[1])
-        out.append(Request(i, prob, nsteps, prec, float(t[i])))
+        spec = (seed * 100_000 + i, sizes[0], sizes[1])
+        if lazy:
+            out.append(Request(i, None, nsteps, prec, float(t[i]), spec=spec, side=W.batch_instance_side(*spec)))
+        else:
+            out.append(Request(i, W.batch_instance(*spec), nsteps, prec, float(t[i])))
     return out
 
 
 def footprint_bytes(prob, precision):
     """Device memory of one simulation (both buffers of every population,
-    status and code array, volumes, balance records, read-out planes)."""
-    pitch = (prob.nx + 63) // 64 * 64
-    plane = pitch * prob.ny
+    status and code array, volumes, balance records, read-out planes); `prob`
+    is a problem or a Request."""
+    nx, ny, ns = prob.dims if isinstance(prob, Request) else (prob.nx, prob.ny, prob.n_species)
+    pitch = (nx + 63) // 64 * 64
+    plane = pitch * ny
     esz = ESZ[precision]
-    ns = prob.n_species
     pops = 18 * plane * esz + 10 * ((ns + 1) // 2) * plane * esz
     words = plane * 4 * (1 + (((ns + 3) // 4) if esz == 2 else 0))
-    items = (pitch // 64) * ((prob.ny + 7) // 8)  # balance records: items of 8 rows or more
+    items = (pitch // 64) * ((ny + 7) // 8)  # balance records: items of 8 rows or more
     return 2 * (pops + words) + plane * 8 + items * 38 * 8 + (4 + ns) * plane * 8
 
 
+def _progress(tag, t0, last, every, requests, active=0):
+    """A progress line on stderr at most every `every` seconds of the run."""
+    now = time.perf_counter() - t0
+    if every and now - last >= every:
+        done = sum(1 for r in requests if r.status != "pending")
+        print(f"# {tag}: t={now:.0f}s completed={done}/{len(requests)} active={active}", file=sys.stderr, flush=True)
+        return now
+    return last
+
+
 class Server:
-    def __init__(self, hbm_cap=200e9, tick=50, autotune=True, keep_fields=False, depth=2):
+    def __init__(self, hbm_cap=200e9, tick=50, autotune=True, keep_fields=False, depth=2, progress=0.0):
         self.hbm_cap = hbm_cap
         self.tick = tick
         self.autotune = autotune
         self.keep_fields = keep_fields
         self.depth = depth  # ticks enqueued ahead of the host before it waits
+        self.progress = progress  # seconds between progress lines (0: none)
 
     def run(self, requests):
         import torch
@@ -95,8 +128,13 @@ class Server:
 
         stream = torch.cuda.Stream()
         if self.autotune:  # measured before the clock starts, once per size class
+            seen = set()
             for r in requests:
-                tuned_seg_rows(r.prob, r.precision, stream)
+                nx, ny, ns = r.dims
+                key = (max(nx, ny), r.precision, ns) if r.prob is None else id(r)
+                if key not in seen:
+                    seen.add(key)
+                    tuned_seg_rows(r.problem(), r.precision, stream)
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
         active = {}  # rid -> (request, sim, remaining, footprint)
         batches = {}  # group -> (member rids, Batch)
@@ -109,16 +147,20 @@ class Server:
         tick_no, done_tick = 0, -1
         used = 0.0
         t0 = time.perf_counter()
+        last = 0.0
         while pending or active:
+            last = _progress("serve", t0, last, self.progress, requests, len(active))
             now = time.perf_counter() - t0
             while pending and pending[0].arrival <= now:
                 r = pending[0]
-                fp = footprint_bytes(r.prob, r.precision)
+                fp = footprint_bytes(r, r.precision)
                 if used + fp > self.hbm_cap and active:
                     break  # wait until memory frees up (a request larger than the cap runs alone)
                 pending.popleft()
-                h = tuned_seg_rows(r.prob, r.precision, stream) if self.autotune else 0
-                sim = Lbrx(r.prob, r.precision, stream=stream.cuda_stream, seg_rows=h)
+                prob = r.problem()
+                h = tuned_seg_rows(prob, r.precision, stream) if self.autotune else 0
+                sim = Lbrx(prob, r.precision, stream=stream.cuda_stream, seg_rows=h)
+                del prob
                 r.start = time.perf_counter() - t0
                 active[r.rid] = [r, sim, r.steps, fp]
                 used += fp
@@ -127,7 +169,7 @@ class Server:
                 continue
             groups = collections.defaultdict(list)
             for rid, (r, sim, rem, fp) in sorted(active.items()):
-                groups[(r.precision, r.prob.n_species)].append(rid)
+                groups[(r.precision, r.dims[2])].append(rid)
             for g, rids in groups.items():
                 members, b = batches.get(g, ((), None))
                 if tuple(rids) != members:
@@ -184,7 +226,7 @@ class Server:
         return summarize(requests, makespan)
 
 
-def run_plain(requests, keep_fields=False, precision=None):
+def run_plain(requests, keep_fields=False, precision=None, progress=0.0):
     """The same requests one at a time in arrival order, each stepped alone
     (in `precision` if given, e.g. the plain FP32 kernels, else in its own)."""
     import torch
@@ -193,12 +235,14 @@ def run_plain(requests, keep_fields=False, precision=None):
 
     stream = torch.cuda.Stream()
     t0 = time.perf_counter()
+    last = 0.0
     for r in sorted(requests, key=lambda r: r.arrival):
+        last = _progress("plain", t0, last, progress, requests)
         wait = r.arrival - (time.perf_counter() - t0)
         if wait > 0:
             time.sleep(wait)
         r.start = time.perf_counter() - t0
-        sim = Lbrx(r.prob, precision or r.precision, stream=stream.cuda_stream)
+        sim = Lbrx(r.problem(), precision or r.precision, stream=stream.cuda_stream)
         sim.step(r.steps)
         try:
             sim.sync()
@@ -223,4 +267,4 @@ def summarize(requests, makespan):
 
 def clone_requests(requests):
     """Fresh copies (same problems, steps, precisions and arrivals)."""
-    return [Request(r.rid, r.prob, r.steps, r.precision, r.arrival) for r in requests]
+    return [Request(r.rid, r.prob, r.steps, r.precision, r.arrival, spec=r.spec, side=r.side) for r in requests]

@@ -358,6 +358,13 @@ def config2(n=4096, seed=2, steps=10000):
     return p
 
 
+def batch_instance_side(seed, smin=64, smax=1024):
+    """The lattice side batch_instance(seed, smin, smax) draws (without
+    generating the instance)."""
+    rng = _rng(10_000 + seed)
+    return int(round(np.exp(rng.uniform(np.log(smin), np.log(smax)))))
+
+
 def batch_instance(seed, smin=64, smax=1024):
     """One instance of the many-simulations workload: the porous-medium
     generator on a square lattice whose side is log-uniform in [smin, smax],
