@@ -103,7 +103,7 @@ def serving(n, interarrival, steps=(200, 2000), cap_gb=200.0, mode="both", progr
         out["plain"] = serve.run_plain(serve.clone_requests(reqs), precision="f32", progress=progress)
         print(f"# serving plain {out['plain']}", file=sys.stderr, flush=True)
     span = reqs[-1].arrival
-    if span < 600 or steps != (1000, 50000) or cap_gb != 200.0:
+    if span < 540 or steps != (1000, 50000) or cap_gb != 200.0:
         out["note"] = ("a short stand-in for the 10-minute stream of 1000-50000-step requests under a 200 GB cap "
                        "(bench.py --serve-requests 600 --serve-interarrival-ms 1000 --serve-steps 1000,50000 runs it)")
     if mode == "both":
@@ -125,7 +125,7 @@ def batched(n_inst, steps, warmup=30, plain_warmup=30):
 
     from paper_1410_3464_amd import workloads as W
     from paper_1410_3464_amd.autotune import table, tuned_seg_rows
-    from paper_1410_3464_amd.lbrx import Batch, Lbrx
+    from paper_1410_3464_amd.lbrx import Batch, Lbrx, LbrxError
 
     probs = [W.batch_instance(50_000 + i) for i in range(n_inst)]
     nodes = sum(p.nx * p.ny for p in probs)
@@ -140,13 +140,20 @@ def batched(n_inst, steps, warmup=30, plain_warmup=30):
     st.synchronize()
     wall_b = time.perf_counter() - t0
     b.close()
-    for s in sims:
-        s.sync()  # raises on a numerical failure
+    # an instance can become numerically unstable (its fields are then
+    # meaningless); both sides run it all the same and the count is reported
+    failed_b = []
+    for i, s in enumerate(sims):
+        try:
+            s.sync()
+        except LbrxError as e:
+            failed_b.append((probs[i].name, str(e)))
         s.close()
     del sims
     print(f"# batched: {n_inst} instances, {nodes} nodes, {wall_b / steps * 1e3:.3f} ms per step",
           file=sys.stderr, flush=True)
     wall_p = 0.0
+    failed_p = []
     t_last = time.perf_counter()
     for i, p in enumerate(probs):
         if time.perf_counter() - t_last > 30:
@@ -159,7 +166,10 @@ def batched(n_inst, steps, warmup=30, plain_warmup=30):
         s.step(steps)
         st.synchronize()
         wall_p += time.perf_counter() - t0
-        s.sync()
+        try:
+            s.sync()
+        except LbrxError:
+            failed_p.append(p.name)
         s.close()
     mb = nodes * steps / wall_b / 1e6
     mp = nodes * steps / wall_p / 1e6
@@ -172,6 +182,7 @@ def batched(n_inst, steps, warmup=30, plain_warmup=30):
         "batched_ms_per_step": round(wall_b / steps * 1e3, 3),
         "one_at_a_time_s": round(wall_p, 3),
         "seg_rows_by_size_class": {f"{k[0]}": v for k, v in table().items() if k[1] == "f32" and k[3] == "batch"},
+        "unstable_instances": {"batched": [f"{n}: {e}" for n, e in failed_b], "one_at_a_time": failed_p},
         **({} if (n_inst, steps) == (256, 5000) else
            {"note": "a shorter stand-in for 256 instances x 5000 steps (bench.py --batch-instances 256 "
                     "--batch-steps 5000 runs it)"}),

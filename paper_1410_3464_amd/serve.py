@@ -260,7 +260,8 @@ def summarize(requests, makespan):
     lat = np.array([r.latency for r in requests]) * 1e3
     ok = sum(r.status == "ok" for r in requests)
     upd = sum(r.updates for r in requests)
-    return {"requests": len(requests), "completed": ok,
+    failed = collections.Counter(r.precision for r in requests if r.status.startswith("failed"))
+    return {"requests": len(requests), "completed": ok, "failed_by_precision": dict(failed),
             "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
             "mlups": round(upd / makespan / 1e6, 1), "makespan_s": round(makespan, 3)}
 
