@@ -1014,8 +1014,8 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
       pull(co, rowin ? Yw : 0, w, validf, withg, fn, gn);
       moments(fn, gn, w, validf, mn);
       unsigned errf = 0;
-      if (validf && (!(mn.rho[0] >= T(0)) || !(mn.rho[1] >= T(0)) || (fluid && !(mn.rho[0] + mn.rho[1] > T(0)))))
-        errf |= ERR_DENSITY;
+      const bool bad = validf && (!(mn.rho[0] >= T(0)) || !(mn.rho[1] >= T(0)) || (fluid && !(mn.rho[0] + mn.rho[1] > T(0))));
+      errf |= bad ? (unsigned)ERR_DENSITY : 0u;
       T ps, q1, q2;
       bool clamped;
       effmass(fluid, mn.rho, ps, q1, q2, clamped, errf);
@@ -1122,11 +1122,13 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
       T Cin[NSA];
 #pragma unroll
       for (int kk = 0; kk < NSA; ++kk) Cin[kk] = T(0);
+      bool any_in_w = false;  // some lane of this row takes shares
       if (NS > 0) {
         bool any_in = false;
 #pragma unroll
         for (int a = 1; a < 5; ++a) any_in |= !(am(a) & TB_WALL) && sf_of(am(a)) == SF_SHARE;
         any_in = any_in && sf == SF_STREAM;
+        any_in_w = __ballot(any_in) != 0ull;
         if (any_in) {
 #pragma unroll
           for (int a = 1; a < 5; ++a)
@@ -1176,20 +1178,24 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
             const bool fx = is_fluid(nt[ax]), fy = is_fluid(nt[ay]);
             const T h = (fx && fy) ? T(0.5) : T(1);
             const bool ownm = !fx && !fy;
-            if (nf) {
-              if constexpr (SFORM) {
-                const T dxp = fx ? nq(ax).ps - ps : T(0), dyp = fy ? nq(ay).ps - ps : T(0);
-                const T dx1 = fx ? nq(ax).q1 - q1 : T(0), dy1 = fy ? nq(ay).q1 - q1 : T(0);
-                const T dx2 = fx ? nq(ax).q2 - q2 : T(0), dy2 = fy ? nq(ay).q2 - q2 : T(0);
-                vps = (dxp + dyp) * h;
-                vq1 = (dx1 + dy1) * h;
-                vq2 = (dx2 + dy2) * h;
-              } else {
-                vps = ownm ? ps : (nq(ax).ps + nq(ay).ps) * h;
-                vq1 = ownm ? q1 : (nq(ax).q1 + nq(ay).q1) * h;
-                vq2 = ownm ? q2 : (nq(ax).q2 + nq(ay).q2) * h;
-              }
+            // (formed on every lane and selected: a branch per diagonal
+            // costs more than the arithmetic)
+            T mps, mq1, mq2;
+            if constexpr (SFORM) {
+              const T dxp = fx ? nq(ax).ps - ps : T(0), dyp = fy ? nq(ay).ps - ps : T(0);
+              const T dx1 = fx ? nq(ax).q1 - q1 : T(0), dy1 = fy ? nq(ay).q1 - q1 : T(0);
+              const T dx2 = fx ? nq(ax).q2 - q2 : T(0), dy2 = fy ? nq(ay).q2 - q2 : T(0);
+              mps = (dxp + dyp) * h;
+              mq1 = (dx1 + dy1) * h;
+              mq2 = (dx2 + dy2) * h;
+            } else {
+              mps = ownm ? ps : (nq(ax).ps + nq(ay).ps) * h;
+              mq1 = ownm ? q1 : (nq(ax).q1 + nq(ay).q1) * h;
+              mq2 = ownm ? q2 : (nq(ax).q2 + nq(ay).q2) * h;
             }
+            vps = nf ? mps : vps;
+            vq1 = nf ? mq1 : vq1;
+            vq2 = nf ? mq2 : vq2;
           }
           if (ex(a) != 0) {
             c1x += T(wf(a) * ex(a)) * vps;
@@ -1230,10 +1236,9 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
           const T r = m.rho[s];
           ux[s] = upx;
           uy[s] = upy;
-          if (r > T(1e-12)) {
-            ux[s] = upx + qdiv<T>(k.tau[s] * Fx[s], r);
-            uy[s] = upy + qdiv<T>(k.tau[s] * Fy[s], r);
-          }
+          const T vx = upx + qdiv<T>(k.tau[s] * Fx[s], r), vy = upy + qdiv<T>(k.tau[s] * Fy[s], r);
+          ux[s] = r > T(1e-12) ? vx : ux[s];
+          uy[s] = r > T(1e-12) ? vy : uy[s];
         }
         const T rt_ = r1 + r2;
         const T urx = qdiv<T>(m.jx[0] + m.jx[1] + T(0.5) * (Fx[0] + Fx[1]), rt_);
@@ -1384,13 +1389,12 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
               }
             }
             // (b) the shares taken this step, at rest
-            if (sf == SF_STREAM) {
+            // (zero at nodes that take none)
+            if (any_in_w) {
 #pragma unroll
               for (int kk = 0; kk < NS; ++kk)
-                if (Cin[kk] != T(0)) {
 #pragma unroll
-                  for (int a = 0; a < 5; ++a) g[kk][a] += SFORM ? Cin[kk] : k.J[kk][a] * Cin[kk];
-                }
+                for (int a = 0; a < 5; ++a) g[kk][a] += SFORM ? Cin[kk] : k.J[kk][a] * Cin[kk];
             }
             // heterogeneous link fluxes (Eq. 29-31, A2): a population heading into a
             // reactive solid comes back next step minus the reactant's (plus the
@@ -1439,9 +1443,9 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
                 nlk[1] += rs && sF ? 1 : 0;
 #pragma unroll
                 for (int kk = 0; kk < NS; ++kk) {
-                  const T d = sF ? dq[1][kk] : dq[0][kk];
-                  const T gv = g[kk][a] + (SFORM ? d * k.iJ1[kk] : d);
-                  g[kk][a] = rs ? gv : g[kk][a];
+                  // (zero on a link to anything but reactive solid)
+                  const T d = rs ? (sF ? dq[1][kk] : dq[0][kk]) : T(0);
+                  g[kk][a] += SFORM ? d * k.iJ1[kk] : d;
                 }
               }
 #pragma unroll
@@ -1484,9 +1488,11 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
 #pragma unroll
             for (int a = 1; a < 5; ++a) {
               const bool lq = is_liq(nt[a]);
-              touched |= lq && (q ? c.xsolid[1] : c.xsolid[0]);
+              const bool on = (q ? c.xsolid[1] : c.xsolid[0]) != 0;
+              touched = touched | (lq & on);
               const VS nv = L.vs[slot(ey(a))][lane + 1 + ex(a)];
-              dv += lq ? (q ? nv.f : nv.d) : 0.0;
+              const double nvq = q ? nv.f : nv.d;
+              dv += lq ? nvq : 0.0;
             }
           }
           double Vn = v_cur;  // (loaded ahead)
@@ -1578,16 +1584,15 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
           // reference codes of the populations stored now (the node's own
           // density, or the one a dissolved node is given)
           const T d0 = dissolved ? rdis[0] : m.rho[0], d1 = dissolved ? rdis[1] : m.rho[1];
-          if (fluid || dissolved) wout |= put_codes(ref_code(d0, k.rb1, SH1, MAX1), ref_code(d1, k.rb2, SH2, MAX2));
+          const uint32_t codes = put_codes(ref_code(d0, k.rb1, SH1, MAX1), ref_code(d1, k.rb2, SH2, MAX2));
+          wout |= (fluid || dissolved) ? codes : 0u;
         }
-        if (!dissolved) {
+        uint32_t nbf = 0u, nbl = 0u;
 #pragma unroll
-          for (int b = 1; b < 9; ++b) wout |= (nt[b] & LF_FLU) << (NBF_SHIFT + b - 1 - 6);
-          if (liq) {
+        for (int b = 1; b < 9; ++b) nbf |= (nt[b] & LF_FLU) << (NBF_SHIFT + b - 1 - 6);
 #pragma unroll
-            for (int b = 1; b < 5; ++b) wout |= (nt[b] & LF_LIQN) << (NBL_SHIFT + b - 1 - 5);
-          }
-        }
+        for (int b = 1; b < 5; ++b) nbl |= (nt[b] & LF_LIQN) << (NBL_SHIFT + b - 1 - 5);
+        wout |= dissolved ? 0u : (nbf | (liq ? nbl : 0u));
       }
       if (!EXPORT) {
         // the rare balances of this row: wave sums in a fixed order, added by lane 0
@@ -1676,7 +1681,12 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
 #pragma unroll
             for (int a = 0; a < 9; ++a) {
               RF<T> rd = ro;
-              if (a != 0 && !dissolved && is_fluid(nt[a])) rd = L.rf[slot(ey(a))][lane + 1 + ex(a)];
+              if (a != 0) {
+                const RF<T> rn = L.rf[slot(ey(a))][lane + 1 + ex(a)];
+                const bool use = !dissolved && is_fluid(nt[a]);
+                rd.r1 = use ? rn.r1 : rd.r1;
+                rd.r2 = use ? rn.r2 : rd.r2;
+              }
               f[0][a] = __builtin_fmaf(f[0][a], k.sc[0], -(k.wsc[0][wcls(a)] * rd.r1));
               f[1][a] = __builtin_fmaf(f[1][a], k.sc[1], -(k.wsc[1][wcls(a)] * rd.r2));
             }
@@ -1691,7 +1701,12 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
 #pragma unroll
             for (int a = 0; a < 9; ++a) {
               RF<T> rd = ro;
-              if (a != 0 && !dissolved && is_fluid(nt[a])) rd = L.rf[slot(ey(a))][lane + 1 + ex(a)];
+              if (a != 0) {
+                const RF<T> rn = L.rf[slot(ey(a))][lane + 1 + ex(a)];
+                const bool use = !dissolved && is_fluid(nt[a]);
+                rd.r1 = use ? rn.r1 : rd.r1;
+                rd.r2 = use ? rn.r2 : rd.r2;
+              }
               if (top_out && ey(a) < 0) rd = RF<T>{T(0), T(0)};
               f[0][a] += o1 - rd.r1;
               f[1][a] += o2 - rd.r2;
