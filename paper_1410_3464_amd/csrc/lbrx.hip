@@ -304,22 +304,26 @@ template <typename T, typename K> __device__ inline T p_cs(const K& k, T rho) {
 // halfway bounce-back against the previous step's masks, which each node keeps
 // in its status word), then runs step n and writes f*(n), g*(n) back into the
 // node's own slots.  Own-slot stores let every written 128-byte line be
-// complete: every lane of a 32-lane group that holds a valid population
-// stores (lanes without one store values that are never read).
+// complete: every lane of a group that shares a line and holds a valid
+// population stores (lanes without one store values that are never read).
 //
-// Work decomposition: one wavefront per item of SW = 64 columns (aligned to
-// the row pitch) by H rows.  The wavefront first computes the moments and
-// effective masses of the two halo columns (x0 - 1, x0 + 64) for its H + 2
-// rows in one pass, then marches down its rows: at row R it pulls row R + 1,
+// Work decomposition: one wavefront per item of IW = 62 columns by H rows.
+// Its 64 lanes hold columns x0 - 1 .. x0 + 62: the item's own columns and one
+// halo column on each side, which the horizontally adjacent items own.  The
+// wavefront marches down its rows: at row R it pulls row R + 1 on every lane,
 // stages that row's psi, phi, node flags, densities and concentrations in a
-// three-row LDS ring, and collides row R against the ring.  Wavefronts never
-// wait for each other, so one wavefront's loads overlap another's arithmetic.
+// three-row LDS ring, and collides row R on its own lanes against the ring.
+// The halo lanes pull the same lines as the neighbouring item's edge lanes,
+// at about the same time (adjacent items are dispatched one after the other),
+// so those lines are read once from memory.  Wavefronts never wait for each
+// other, so one wavefront's loads overlap another's arithmetic.
 //
 // Memory access is through raw buffer descriptors: a per-lane 32-bit offset
 // (one per link direction, shared by both components and all species) plus a
 // uniform offset for the population plane.
-constexpr int SW = 64;    // item width: one lane per column
-constexpr int HMAX = 30;  // most rows per item: both halo columns (H + 2 rows each) fit one wavefront
+constexpr int SW = 64;       // lanes: one column each
+constexpr int IW = SW - 2;   // columns an item owns (lanes 1 .. 62)
+constexpr int HMAX = 30;     // most rows per item
 // wavefronts per workgroup, each with its own item
 #ifndef LBRX_WPB
 #define LBRX_WPB 1
@@ -387,23 +391,16 @@ template <typename T, int NS, int SM> struct WaveLds {
   // flow reference rows (FP32 and 16-bit storage), solute reference rows (16-bit storage)
   static constexpr bool REFS = sm_dev(SM) || std::is_same<T, float>::value;
   static constexpr int NRF = REFS ? 3 : 1;
-  static constexpr int NHF = REFS ? 2 : 1;
   static constexpr int NCF = sm_dev(SM) ? 3 : 1;
-  static constexpr int NHC = sm_dev(SM) ? 2 : 1;
-  // ring rows (R - 1, R, R + 1 in rotation) x columns x0 - 1 .. x0 + 64
+  // ring rows (R - 1, R, R + 1 in rotation) x lanes; lane l at index l + 1
+  // (indices 0 and SW + 1 are read only by the halo lanes, whose row-R
+  // results are not used)
   PQ<T> pq[3][SW + 2];
   T r1[3][SW + 2], r2[3][SW + 2];
   T C[NSA][3][SW + 2];
   RF<T> rf[NRF][SW + 2];
   VS vs[3][SW + 2];
   T Cf[NSA][NCF][SW + 2];
-  // halo columns (left, right) for rows y0 - 1 .. y0 + H
-  PQ<T> hpq[2][HMAX + 2];
-  T hr1[2][HMAX + 2], hr2[2][HMAX + 2];
-  T hC[NSA][2][HMAX + 2];
-  RF<T> hrf[NHF][HMAX + 2];
-  VS hvs[2][HMAX + 2];
-  T hCf[NSA][NHC][HMAX + 2];
   double rare[NRARE_SLOTS];
 };
 
@@ -594,7 +591,7 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
   const int item = blk * WPB + wv;
   if (item >= c.nitems) return;  // whole wavefront
   const int sx = item % c.strips, sy = item / c.strips;
-  const int x0 = sx * SW, y0 = sy * c.seg_rows;
+  const int x0 = sx * IW, y0 = sy * c.seg_rows;
   const int y1 = min(y0 + c.seg_rows, c.ny);
   const int nrow = y1 - y0;
   const int nx = c.nx, ny = c.ny;
@@ -906,11 +903,12 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
     co[2] = (unsigned)xp * PE;
   };
 
-  // this lane's column
-  int Xw = x0 + lane;
+  // this lane's column: the item's own columns on lanes 1 .. IW, a halo
+  // column on lanes 0 and SW - 1
+  int Xw = x0 - 1 + lane;
   const bool colin = wrap(Xw, nx, c.per_x);
-  const int X = x0 + lane;
-  const bool colown = X < nx;
+  const int X = x0 - 1 + lane;
+  const bool colown = lane >= 1 && lane <= IW && X < nx;
   unsigned co[3];
   col_offsets(colin ? Xw : 0, co);
 
@@ -921,52 +919,6 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
     return in ? v : (uint32_t)TB_WALL;
   };
   uint32_t w_cur = 0, w_next = word_row(y0 - 1);
-  // (loaded before the halo columns, so that the loads there separate it from
-  // its first use)
-
-  // ------------------------------------------------------------ halo columns
-  {
-    const int hs = lane >> 5, hr = lane & 31;
-    const bool hact = hr < nrow + 2;
-    int HX = hs ? x0 + SW : x0 - 1, HY = y0 - 1 + hr;
-    const bool indom = hact && wrap(HX, nx, c.per_x) && wrap_y(HY);
-    const uint32_t hwl = bload<uint32_t>(rt, gate(indom, (unsigned)HX * 4u + (unsigned)HY * upitch * 4u), 0u);
-    const uint32_t hw = indom ? hwl : (uint32_t)TB_WALL;
-    const int t = (int)(hw & TB_T);
-    const bool fluid = indom && t == T_FLUID;
-    const bool validf = indom && (t == T_FLUID || (hw & TB_STR));
-    const bool withg = indom && sf_of(hw) != SF_NONE;
-    unsigned co[3];
-    col_offsets(indom ? HX : 0, co);
-    T f[2][9], g[NSA][5];
-    pull(co, indom ? HY : 0, hw, validf, withg, f, g);
-    Mom<T, NS> m;
-    moments(f, g, hw, validf, m);
-    T ps, q1, q2;
-    bool cl;
-    unsigned ef = 0;
-    effmass(fluid, m.rho, ps, q1, q2, cl, ef);
-    if (hact) {
-      const uint32_t fl = indom ? (flags_w(hw) | ((fluid && (double)m.rho[0] > thr) ? LF_LIQN : 0u)) : (uint32_t)TB_WALL;
-      L.hpq[hs][hr] = PQ<T>{ps, q1, q2, flags_as<T>(fl)};
-      if (!EXPORT) L.hvs[hs][hr] = solid_dv((fl & LF_LIQN) != 0, hw, m);
-      L.hr1[hs][hr] = m.rho[0];
-      L.hr2[hs][hr] = m.rho[1];
-#pragma unroll
-      for (int kk = 0; kk < NSA; ++kk) L.hC[kk][hs][hr] = m.C[kk];
-      if constexpr (REFS) {
-        RF<T> r;
-        T cf[NSA];
-        wref(m, r, cf);
-        L.hrf[hs][hr] = r;
-        if constexpr (DEV) {
-#pragma unroll
-          for (int kk = 0; kk < NSA; ++kk) L.hCf[kk][hs][hr] = cf[kk];
-        }
-      }
-    }
-  }
-
   // per-lane balance contributions over the item's rows, in FP64: the gas
   // component's homogeneous source (the liquid component's is its exact
   // negative), the solute sources and the heterogeneous exchange
@@ -1044,23 +996,6 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
         if constexpr (DEV) {
 #pragma unroll
           for (int kk = 0; kk < NSA; ++kk) L.Cf[kk][sp][cl] = cf[kk];
-        }
-      }
-      if (lane < 2) {
-        const int ce = lane ? SW + 1 : 0;
-        const int hr = Rn - (y0 - 1);
-        L.pq[sp][ce] = L.hpq[lane][hr];
-        if (!EXPORT) L.vs[sp][ce] = L.hvs[lane][hr];
-        L.r1[sp][ce] = L.hr1[lane][hr];
-        L.r2[sp][ce] = L.hr2[lane][hr];
-#pragma unroll
-        for (int kk = 0; kk < NSA; ++kk) L.C[kk][sp][ce] = L.hC[kk][lane][hr];
-        if constexpr (REFS) {
-          L.rf[sp][ce] = L.hrf[lane][hr];
-          if constexpr (DEV) {
-#pragma unroll
-            for (int kk = 0; kk < NSA; ++kk) L.Cf[kk][sp][ce] = L.hCf[kk][lane][hr];
-          }
         }
       }
     }
@@ -1648,21 +1583,25 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
         // next step).  Here the values are put in the form they are stored in
         // and the offsets set; the stores follow the row (every lane, every
         // iteration, out of range where nothing is stored).
-        so_t = (unsigned)X * 4u + (unsigned)R * upitch * 4u;
+        // (only the item's own lanes store; the halo lanes' columns belong to
+        // the neighbouring items)
+        so_t = gate(own, (unsigned)X * 4u + (unsigned)R * upitch * 4u);
         wst = wout;
         const unsigned long long bf = __ballot(storef);
         const unsigned long long bg = __ballot(storeg);
-        // a 128-byte line holds the flow slots of 128 / PE lanes (32 for
+        // a 128-byte line holds the flow slots of 128 / PE columns (32 for
         // 16-bit pairs, 16 for FP32, 8 for FP64), the solute slots of
-        // 128 / PEG lanes; the solute code words, 32 lanes
-        constexpr int G = 128 / PE;
-        constexpr unsigned long long GM = (1ull << G) - 1ull;
-        const int gl = lane & ~(G - 1);
-        const bool gf = ((bf >> gl) & GM) != 0ull;
-        constexpr int GG = 128 / PEG;
-        constexpr unsigned long long GGM = (1ull << GG) - 1ull;
-        const bool gg = ((bg >> (lane & ~(GG - 1))) & GGM) != 0ull;
-        const bool gw = ((bg >> (lane & 32)) & 0xffffffffull) != 0ull;
+        // 128 / PEG columns; the solute code words, 32 columns.  The lanes
+        // whose columns share this lane's line (lanes are columns x0 - 1 ..):
+        auto line_lanes = [&](int lg) -> unsigned long long {
+          const int lo = ((X >> lg) << lg) - (x0 - 1);
+          const int a0 = lo < 0 ? 0 : lo, a1 = lo + (1 << lg) - 1 > SW - 1 ? SW - 1 : lo + (1 << lg) - 1;
+          return (~0ull >> (SW - 1 - a1)) & (~0ull << a0);
+        };
+        constexpr int LGF = __builtin_ctz(128 / PE), LGG = __builtin_ctz(128 / PEG);
+        const bool gf = own && (bf & line_lanes(LGF)) != 0ull;
+        const bool gg = own && (bg & line_lanes(LGG)) != 0ull;
+        const bool gw = own && (bg & line_lanes(5)) != 0ull;
         const unsigned xo = (unsigned)X * PE;
         so_f = gate(gf, xo + (unsigned)R * RSF);
         if constexpr (REFS) {
@@ -2377,7 +2316,7 @@ lbrx_status lbrx_create(const lbrx_params* p, void* hip_stream, lbrx_ctx** out) 
     const int v = atoi(e);
     if (v >= 1 && v <= HMAX) c.seg_rows = v;
   }
-  c.strips = c.pitch / SW;
+  c.strips = (c.nx + IW - 1) / IW;
   c.nitems = c.strips * ((p->ny + c.seg_rows - 1) / c.seg_rows);
   c.nblocks = (c.nitems + WPB - 1) / WPB;
   // byte sizes of the population and status arrays (below 4 GiB, checked in validate)
