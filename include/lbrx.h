@@ -140,8 +140,9 @@ typedef struct {
   const double* rho2;       /* >= 0 at fluid nodes */
   const double* C0;         /* used at nodes that start liquid; may be NULL if n_species == 0 */
   /* work decomposition: rows per work item of the step kernel (each item is
-     64 columns by seg_rows rows, one wavefront), 1..30; 0 picks 16 for
-     FP64 storage and 12 otherwise.  It changes the speed, not the result. */
+     62 columns by seg_rows rows, one 64-lane wavefront that also pulls the
+     column on either side), 1..30; 0 picks 16.  It changes the speed, not
+     the result. */
   int32_t seg_rows;
   /* effective mass psi_1 = sqrt(psi_prefactor (p_EOS - rho1/3) / G11) (Eq. 13).
      0 selects 2, the value for which the weights of Eq. 11 reproduce the EOS

@@ -1,6 +1,6 @@
 """Tile-schedule autotuner for the step kernel.
 
-The kernel's work item is 64 columns by `seg_rows` rows, one wavefront.  Short
+The kernel's work item is 62 columns by `seg_rows` rows, one wavefront.  Short
 items balance better on small lattices; long items repeat fewer ring rows (two
 per item) on large ones.  The best value depends on lattice size, storage
 precision and on how full the device is, so it is measured: each candidate runs

@@ -1789,7 +1789,7 @@ __global__ __launch_bounds__(LSUM_THREADS) void k_ledger_sum(const double* led, 
 }
 
 // ---------------------------------------------------------------- host side
-constexpr int SEG_ROWS = 12;      // default rows per item (LBRX_SEG_ROWS overrides, 1..HMAX)
+constexpr int SEG_ROWS = 16;      // default rows per item (LBRX_SEG_ROWS overrides, 1..HMAX)
 constexpr int SEG_ROWS_F64 = 16;  // FP64 storage (one wavefront per SIMD): taller items
 // Steps per captured HIP graph of launches: a multiple of 6, the period of
 // the step phases (buffer parity and rho_max slot), so that one graph serves
