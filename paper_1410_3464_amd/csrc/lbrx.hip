@@ -1529,8 +1529,9 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
         for (int b = 1; b < 5; ++b) nbl |= (nt[b] & LF_LIQN) << (NBL_SHIFT + b - 1 - 5);
         wout |= dissolved ? 0u : (nbf | (liq ? nbl : 0u));
       }
-      if (!EXPORT) {
-        // the rare balances of this row: wave sums in a fixed order, added by lane 0
+      // the rare balances of this row: wave sums in a fixed order, added by
+      // lane 0 (one test for the whole row first: most rows have none)
+      if (!EXPORT && __ballot(r_diss | r_strand | r_l2g | r_g2l | r_pre) != 0ull) {
         const unsigned long long bd = __ballot(r_diss), bs = __ballot(r_strand);
         const unsigned long long bl = __ballot(r_l2g), bgl = __ballot(r_g2l), bp = __ballot(r_pre);
         if (bd) {
