@@ -7,9 +7,10 @@
 //   * State between steps: post-collision populations f*, g* of every node in
 //     its own slots (row-interleaved structure of arrays: population q of row
 //     y at (y * NP + q) * pitch + x), one 32-bit status word per node (type,
-//     liquid marks, and which neighbours were fluid / liquid when the
+//     the solute it holds, and which neighbours were fluid / liquid when the
 //     populations were written), the FP64 solid / precipitate volume.
-//   * One wavefront owns a 64-column by H-row item and marches down it.  Per
+//   * One wavefront owns a 62-column by H-row item (its 64 lanes also hold
+//     the column on either side) and marches down it.  Per
 //     row it pulls the next row's populations along the links (halfway
 //     bounce-back where the status word names no fluid neighbour), forms the
 //     moments (Eq. 9, 23) and effective masses psi_1, phi_1, phi_2 (Eq. 13,
@@ -534,8 +535,9 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
 
   // XCD-aware order: consecutive workgroups are dealt round-robin to the 8
   // XCDs; each XCD gets a contiguous band of items (of a batch's table), so
-  // that the halo rows two vertically neighbouring items share sit in the
-  // same L2.
+  // that horizontally adjacent items (whose halo lanes read each other's
+  // edge columns) run at about the same time, and the rows two vertically
+  // neighbouring items share sit in the same L2.
   const int nb = gridDim.x;
   const int bid = blockIdx.x;
   const int xcd = bid & 7, loc = bid >> 3;
@@ -1576,16 +1578,15 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
         }
       } else {
         // -------------------------------------------------- own-slot stores
-        // Every lane writes its node's slots at the unwrapped column (a lane
-        // past nx writes into the row padding).  A group of lanes that share a
-        // 128-byte line writes all its lanes when any of them holds valid
-        // populations, so that lines are written whole; a lane without valid
-        // populations writes values nobody reads (its slots are not pulled from
-        // next step).  Here the values are put in the form they are stored in
-        // and the offsets set; the stores follow the row (every lane, every
-        // iteration, out of range where nothing is stored).
-        // (only the item's own lanes store; the halo lanes' columns belong to
-        // the neighbouring items)
+        // The item's own lanes (columns below nx) write their nodes' slots;
+        // the halo lanes' columns belong to the neighbouring items.  Own
+        // lanes whose columns share a 128-byte line write all of them when
+        // any holds valid populations, so that lines are written whole; a
+        // lane without valid populations writes values nobody reads (its
+        // slots are not pulled from next step).  Here the values are put in
+        // the form they are stored in and the offsets set; the stores follow
+        // the row (every lane, every iteration, out of range where nothing
+        // is stored).
         so_t = gate(own, (unsigned)X * 4u + (unsigned)R * upitch * 4u);
         wst = wout;
         const unsigned long long bf = __ballot(storef);
