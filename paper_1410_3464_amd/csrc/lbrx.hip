@@ -1668,7 +1668,10 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
               const bool nbr = a != 0 && !donor && is_liq(nt[a]);
 #pragma unroll
               for (int kk = 0; kk < NS; ++kk) {
-                const T cr = nbr ? L.Cf[kk][slot(ey(a))][lane + 1 + ex(a)] : co_[kk];
+                // (read on every lane and selected: a read under the condition
+                // is a branch per direction and species)
+                const T cn = a != 0 ? L.Cf[kk][slot(ey(a))][lane + 1 + ex(a)] : co_[kk];
+                const T cr = nbr ? cn : co_[kk];
                 g[kk][a] = __builtin_fmaf(g[kk][a], k.scg[kk], -(k.Jsc[kk][a == 0 ? 0 : 1] * cr));
               }
             }
