@@ -188,6 +188,9 @@ static int validate(const orc_params* p, char* err, int errlen) {
   }
   if (!(p->liquid_frac >= 0.0 && p->liquid_frac < 1.0)) return fail(err, errlen, "liquid_frac in [0,1)");
   if (p->outlet_top && (p->periodic_y || p->ny < 2)) return fail(err, errlen, "a free outlet needs walls in y and ny >= 2");
+  if (p->sub_species < -1 || p->sub_species >= p->n_species) return fail(err, errlen, "bad subtracted species");
+  if (p->sub_species >= 0 && !(p->sub_total > 0.0 && p->sub_total < 1e300))
+    return fail(err, errlen, "the total liquid concentration per density must be > 0");
   return 1;
 }
 
@@ -533,6 +536,18 @@ static void mark_liquid(orc_sim* s) {
   }
 }
 
+/* Sec. 4.1 (and Sec. 2's liquid of A, B, E, F): with sub_species = m, only
+ * the other aqueous species are transported in effect; at a liquid node
+ * C_m = sub_total * rho_1 - sum of the others.  Applied to the
+ * concentrations the step uses (after the amendments of step 3) and to the
+ * exported ones. */
+static double subtracted(const orc_sim* s, const double* C, int i) {
+  double c = s->p.sub_total * s->rho[i];
+  for (int k = 0; k < s->ns; ++k)
+    if (k != s->p.sub_species) c -= C[k * s->N + i];
+  return c;
+}
+
 int orc_step(orc_sim* s, int nsteps) {
   const orc_params* p = &s->p;
   const int N = s->N, ns = s->ns, nx = p->nx, ny = p->ny;
@@ -565,6 +580,12 @@ int orc_step(orc_sim* s, int nsteps) {
       if (s->liq[i] && s->sflag[i] != SF_STREAM) n_g2l += 1.0;
     }
     if (mliq < s->margin_liq) s->margin_liq = mliq;
+    /* 3b. the subtracted species at liquid nodes (Sec. 4.1) */
+    if (p->sub_species >= 0) {
+      PAR_FOR
+      for (int i = 0; i < N; ++i)
+        if (s->liq[i]) s->C[p->sub_species * N + i] = subtracted(s, s->C, i);
+    }
     s->led.n_liq_to_gas += n_l2g;   /* counts: exact in any order */
     s->led.n_gas_to_liq += n_g2l;
 
@@ -962,6 +983,10 @@ void orc_fields(orc_sim* s, double* rho1, double* rho2, double* ux, double* uy,
         else if (sf == SF_HOLD) c = s->C[k * N + i];
         C[k * N + i] = c;
       }
+  /* the subtracted species at liquid nodes, from the exported others */
+  if (C && s->p.sub_species >= 0)
+    for (int i = 0; i < N; ++i)
+      if (s->liq[i]) C[s->p.sub_species * N + i] = subtracted(s, C, i);
   if (ledger) *ledger = s->led;
   if (rho_max_prev) *rho_max_prev = s->rho_max_prev;
 }

@@ -71,6 +71,11 @@ typedef struct {
   double het_mvol[ORC_MAX_RXN];      /* molar volume x specific area per link */
   int32_t outlet_top;     /* 1: the side beyond y = ny - 1 is a free outlet with zero
                              gradient of every variable (Sec. 5.1); needs periodic_y = 0 */
+  int32_t sub_species;    /* Sec. 4.1: the aqueous species whose concentration at a liquid
+                             node is the total liquid concentration minus the others
+                             (not transported in effect); -1: none */
+  double sub_total;       /* the total liquid concentration per unit rho_1 (> 0 when
+                             sub_species >= 0) */
 } orc_params;
 
 /* cumulative balance ledger, all FP64 */

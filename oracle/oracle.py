@@ -38,6 +38,8 @@ class _Params(C.Structure):
         ("het_surface", C.c_int32 * MAXR), ("het_mode", C.c_int32 * MAXR), ("het_irrev", C.c_int32 * MAXR),
         ("het_k", C.c_double * MAXR), ("het_Ceq", C.c_double * MAXR), ("het_mvol", C.c_double * MAXR),
         ("outlet_top", C.c_int32),
+        ("sub_species", C.c_int32),
+        ("sub_total", C.c_double),
     ]
 
 
@@ -134,6 +136,8 @@ def _params(prob, psi_literal=False):
         p.het_irrev[i] = int(r.irreversible)
         p.het_k[i], p.het_Ceq[i], p.het_mvol[i] = r.k, r.C_eq, r.molar_volume
     p.outlet_top = int(prob.outlet_top)
+    p.sub_species = int(getattr(prob, "subtract_species", -1))
+    p.sub_total = float(getattr(prob, "subtract_total", 0.0))
     return p
 
 

@@ -147,6 +147,10 @@ class Problem:
     rho20: float = 0.003
     liquid_frac: float = 0.5
     psi_prefactor: float = 0.0  # 0: 2 (weights of Eq. 11 reproduce Eq. 12); 6: as printed in Eq. 13
+    # Sec. 4.1: species whose concentration at a liquid node is the total liquid
+    # concentration (subtract_total * rho_1) minus the others; -1: none
+    subtract_species: int = -1
+    subtract_total: float = 0.0
     species: list = field(default_factory=list)
     hom: list = field(default_factory=list)
     het: list = field(default_factory=list)

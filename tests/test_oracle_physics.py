@@ -363,6 +363,29 @@ def test_first_order_decay_closed_form():
     assert np.allclose(F["C"][0] + F["C"][1], 0.7, rtol=1e-13, atol=0)
 
 
+def test_subtracted_species_closed_form():
+    """Sec. 4.1: with A taken as the total liquid concentration (0.7 rho_1, rho_1
+    = 1) minus the others, a uniform first-order A -> B gives C_B(n) =
+    0.7 (1 - (1 - k)^n) although A's own populations start at zero (they are
+    not what A is); the exported C_A is 0.7 - C_B.  Without the subtraction
+    the same start has no A and no reaction."""
+    k, n = 1e-2, 300
+    sp = [W.Species("A"), W.Species("B")]
+    C0 = np.zeros((2, 4, 4))
+    p = W.uniform_problem(4, 4, rho1=1.0, species=sp, C0=C0,
+                          hom=[W.HomRxn("first_order", re=(0, -1), pr=(1, -1), k=k)])
+    s = OracleSim(p.copy(subtract_species=0, subtract_total=0.7))
+    s.step(n)
+    F = s.fields()
+    assert np.allclose(F["C"][1], 0.7 * (1 - (1 - k) ** n), rtol=1e-12, atol=0)
+    assert np.allclose(F["C"][0] + F["C"][1], 0.7, rtol=1e-13, atol=0)
+    s.close()
+    s = OracleSim(p)
+    s.step(n)
+    assert np.all(s.fields()["C"] == 0.0)
+    s.close()
+
+
 @pytest.mark.parametrize("surface,enhanced", [((W.SOLID_D,), True), ((W.SOLID_F,), False)])
 def test_surface_enhanced_rate_closed_form(surface, enhanced):
     """A two-row liquid channel between rows of dissolvable solid (no surface
