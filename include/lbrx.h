@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define LBRX_ABI_VERSION 5u
+#define LBRX_ABI_VERSION 6u
 #define LBRX_MAX_SPECIES 8
 #define LBRX_MAX_RXN 8
 
@@ -158,6 +158,14 @@ typedef struct {
   void* (*dev_alloc)(uint64_t bytes, void* user);
   void (*dev_free)(void* ptr, void* user);
   void* alloc_user;
+  /* Sec. 4.1: the aqueous species (0 .. n_species - 1) whose concentration at
+     a liquid node is the total liquid concentration, subtract_total x rho1,
+     minus the other species (its own transport does not enter what it is;
+     its balance entries are not a conservation record); -1: none.
+     subtract_total > 0 when a species is subtracted (the paper takes the
+     total from the liquid's composition, which needs its molar masses). */
+  int32_t subtract_species;
+  double subtract_total;
 } lbrx_params;
 
 /* Cumulative balances, FP64.  With M_s the total of component s and S_k the

@@ -152,6 +152,8 @@ struct KConst {
   // (GROWS reactions on that surface, else 0), and the solid volume change per
   // unit flux on a link from a liquid node (-Vbar CONSUMES, +Vbar MINERAL, else 0)
   double xgv[2][LBRX_MAX_RXN], xsv[2][LBRX_MAX_RXN];
+  int sub;        // the species taken by subtraction at liquid nodes (Sec. 4.1), -1: none
+  double sub_tot; // total liquid concentration per unit rho_1
   int xgrow[2], xsolid[2];  // some reaction of that kind runs on that surface
 };
 
@@ -172,6 +174,7 @@ template <typename T> struct KT {
   // FP32 solute weights of Eq. 22 as stored: J1' on a 2^-26 grid and
   // J0' = 1 - 4 J1', so that the weights sum to one exactly; 1 / (2 J1'), 1 / J1'
   T Jp0[LBRX_MAX_SPECIES], Jp1[LBRX_MAX_SPECIES], hJ[LBRX_MAX_SPECIES], iJ1[LBRX_MAX_SPECIES];
+  T sub_tot;
   // 16-bit storage: deviation scales (powers of two) and reference-code bases
   T sc[2], isc[2], wsc[2][3];               // flow: scale, 1/scale, w (rest, axis, diagonal) x scale
   T scg[LBRX_MAX_SPECIES], iscg[LBRX_MAX_SPECIES], Jsc[LBRX_MAX_SPECIES][2];
@@ -878,15 +881,33 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
   // times -Vbar (CONSUMES) or +Vbar (MINERAL), summed in reaction order.
   // Formed once per node where its moments are staged, so that a solid node
   // adds up its neighbours' values.
+  // Sec. 4.1: with a subtracted species m, a liquid node's C_m is the total
+  // liquid concentration (sub_tot rho_1) minus the other species, in species
+  // order (the same operations as the plain definition)
+  auto subtract = [&](T (&C)[NS > 0 ? NS : 1], T rho1) {
+    if (NS > 1 && c.sub >= 0) {
+      T cs = k.sub_tot * rho1;
+#pragma unroll
+      for (int kk = 0; kk < NS; ++kk) cs -= kk != c.sub ? C[kk] : T(0);
+#pragma unroll
+      for (int kk = 0; kk < NS; ++kk) C[kk] = kk == c.sub ? cs : C[kk];
+    }
+  };
   const bool any_xsolid = NS > 0 && (c.xsolid[0] || c.xsolid[1]);
   auto solid_dv = [&](bool liqn, uint32_t w, const Mom<T, NS>& m) -> VS {
     VS o{0.0, 0.0};
     if (any_xsolid) {
       const int nsf = sf_of(w);
       const bool has = nsf == SF_STREAM || nsf == SF_HOLD;
+      // the concentrations the node's own collision sees (none if it has
+      // just become liquid without content; the subtracted species derived)
+      T ce[NS > 0 ? NS : 1];
+#pragma unroll
+      for (int kk = 0; kk < (NS > 0 ? NS : 1); ++kk) ce[kk] = has ? m.C[kk] : T(0);
+      subtract(ce, m.rho[0]);
       for (int r = 0; r < c.nhet; ++r) {
-        const T cr = sel<NS>(m.C, c.xre[r]);
-        T v = k.xkap[r] * ((has ? cr : T(0)) - k.xCeq[r]);
+        const T cr = sel<NS>(ce, c.xre[r]);
+        T v = k.xkap[r] * (cr - k.xCeq[r]);
         if (c.xirrev[r] && v < T(0)) v = T(0);
         o.d += c.xsv[0][r] * (double)v;
         o.f += c.xsv[1][r] * (double)v;
@@ -1082,6 +1103,14 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
 #pragma unroll
             for (int a = 0; a < 5; ++a) g[kk][a] = T(0);
           }
+        }
+        if (NS > 1 && c.sub >= 0) {
+          T cd[NSA];
+#pragma unroll
+          for (int kk = 0; kk < NSA; ++kk) cd[kk] = m.C[kk];
+          subtract(cd, m.rho[0]);
+#pragma unroll
+          for (int kk = 0; kk < NSA; ++kk) m.C[kk] = liq ? cd[kk] : m.C[kk];
         }
       }
 
@@ -1568,12 +1597,14 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
             o[2 * c.plane + idx] = 0.0;
             o[3 * c.plane + idx] = 0.0;
           }
-          // the solute each node holds once the shares in transit are delivered
+          // the solute each node holds once the shares in transit are
+          // delivered (a subtracted species derived from the others there)
+          T cv[NSA];
 #pragma unroll
-          for (int kk = 0; kk < NS; ++kk) {
-            const T cv = sf == SF_STREAM ? m.C[kk] + Cin[kk] : (sf == SF_HOLD ? m.C[kk] : T(0));
-            o[(size_t)(4 + kk) * c.plane + idx] = (double)cv;
-          }
+          for (int kk = 0; kk < NSA; ++kk) cv[kk] = sf == SF_STREAM ? m.C[kk] + Cin[kk] : (sf == SF_HOLD ? m.C[kk] : T(0));
+          if (liq) subtract(cv, m.rho[0]);
+#pragma unroll
+          for (int kk = 0; kk < NS; ++kk) o[(size_t)(4 + kk) * c.plane + idx] = (double)cv[kk];
           o[(size_t)(4 + NS) * c.plane + idx] = liq ? 1.0 : 0.0;
         }
       } else {
@@ -1939,6 +1970,9 @@ std::string validate(const lbrx_params* p) {
       return "surface_factor must be positive and finite";
   }
   if (!(p->psi_prefactor >= 0.0 && p->psi_prefactor < 1e300)) return "psi_prefactor must be 0 (default) or positive";
+  if (p->subtract_species < -1 || p->subtract_species >= p->n_species) return "subtract_species must be -1 or a species index";
+  if (p->subtract_species >= 0 && !(p->subtract_total > 0.0 && p->subtract_total < 1e300))
+    return "subtract_total must be > 0 when a species is subtracted";
   if (!p->dev_alloc != !p->dev_free) return "dev_alloc and dev_free must be given together";
   for (int r = 0; r < p->n_het; ++r) {
     const lbrx_het_rxn& h = p->het[r];
@@ -2231,6 +2265,7 @@ void fill_kt(KT<T>& k, const lbrx_params* p, const KConst& c, const double* D) {
   k.rho10 = (T)c.rho10;
   k.r_rho10 = (T)(c.rho10 > 0.0 ? 1.0 / c.rho10 : 0.0);
   k.rho20 = (T)c.rho20;
+  k.sub_tot = (T)c.sub_tot;
   k.r_rho20 = (T)(c.rho20 > 0.0 ? 1.0 / c.rho20 : 0.0);
   for (int q = 0; q < LBRX_MAX_SPECIES; ++q) {
     k.omg[q] = (T)c.omg[q];
@@ -2341,6 +2376,8 @@ lbrx_status lbrx_create(const lbrx_params* p, void* hip_stream, lbrx_ctx** out) 
   c.G11 = p->G11;
   c.rG11 = p->G11 != 0.0 ? 1.0 / p->G11 : 0.0;
   c.psi_pre = p->psi_prefactor > 0.0 ? p->psi_prefactor : 2.0;
+  c.sub = p->subtract_species;
+  c.sub_tot = p->subtract_species >= 0 ? p->subtract_total : 0.0;
   c.G12 = p->G12;
   c.G21 = p->G21;
   c.w1 = p->w_adh[0];

@@ -14,7 +14,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbrx.so")
 
-ABI_VERSION = 5
+ABI_VERSION = 6
 MAXS = 8
 MAXR = 8
 F64, F32, F16DEV, BF16DEV = 0, 1, 2, 3
@@ -58,6 +58,7 @@ class Params(C.Structure):
         ("node_type", C.c_void_p), ("V0", C.c_void_p), ("rho1", C.c_void_p), ("rho2", C.c_void_p),
         ("C0", C.c_void_p), ("seg_rows", C.c_int32), ("psi_prefactor", C.c_double),
         ("dev_alloc", C.c_void_p), ("dev_free", C.c_void_p), ("alloc_user", C.c_void_p),
+        ("subtract_species", C.c_int32), ("subtract_total", C.c_double),
     ]
 
 
@@ -196,6 +197,8 @@ def make_params(prob, precision="f64", seg_rows=0):
         h.surface = sum(1 << t for t in r.surface)
         h.surface_factor = r.surface_factor
     p.psi_prefactor = float(prob.psi_prefactor)
+    p.subtract_species = int(getattr(prob, "subtract_species", -1))
+    p.subtract_total = float(getattr(prob, "subtract_total", 0.0))
     p.n_het = len(prob.het)
     for i, r in enumerate(prob.het):
         h = p.het[i]

@@ -327,3 +327,21 @@ def test_invalid_params_rejected():
     sp[0] = W.Species("A", 1.0, 1.0)
     with pytest.raises(LbrxError):
         Lbrx(p.copy(species=sp), "f64")
+
+
+@pytest.mark.parametrize("case,precision,tol", [("droplet", "f64", 1e-12), ("porous", "f64", 1e-12),
+                                                ("droplet", "f32", 1e-5)])
+def test_parity_subtracted_species(case, precision, tol):
+    """A (species 0) taken by subtraction (Sec. 4.1): at a liquid node its
+    concentration is the total liquid concentration, 0.14 rho_1 (about 1 in
+    the liquid), minus the other species.  The droplet (A -> B first order)
+    over 300 steps and the 130 x 70 porous medium (A in the gas-exchange
+    reaction; B, E, F transported, with surface reactions) over 200 steps
+    match the oracle field by field."""
+    if case == "droplet":
+        prob = W.config0().copy(subtract_species=0, subtract_total=0.14, name="droplet-sub")
+        steps = [1, 50, 300] if precision == "f64" else [1, 10, 100]
+    else:
+        prob = W.config1(nx=130, ny=70, seed=11).copy(subtract_species=0, subtract_total=0.14, name="porous-sub")
+        steps = [1, 50, 200]
+    _run_pair(prob, precision, steps, tol)
