@@ -259,9 +259,10 @@ lbrx_status lbrx_fields_noalloc(lbrx_ctx* ctx, lbrx_fields_out* out);
  *     host buffer `buf` of `bytes` (>= lbrx_state_bytes); LBRX_E_INVAL if too
  *     small; a failed context cannot be saved (its sticky error is returned).
  *   lbrx_load_state:  replaces the state of `ctx` by a saved one.  `ctx` must
- *     have been created with the same lattice size, precision, species count
- *     and seg_rows (LBRX_E_INVAL otherwise, state unchanged); other
- *     parameters may differ and apply from the next step.  Enqueued on the
+ *     have been created with the same lattice size, boundaries (`periodic`
+ *     bits, the free outlet included), precision, species count and seg_rows
+ *     (LBRX_E_INVAL otherwise, state unchanged); other parameters may differ
+ *     and apply from the next step.  Enqueued on the
  *     context's stream after its pending work; returns after the copy.
  * Loading a state saved after N steps and stepping M more gives fields bit
  * for bit equal to N + M steps without the checkpoint. */

@@ -2599,16 +2599,19 @@ lbrx_status lbrx_sync(lbrx_ctx* x) {
 namespace {
 
 // ------------------------------------------------------------ checkpoints
-// State blob: a header naming the layout, then the current populations, status
-// words, solute code words, solid volumes, rho_max partials and balance records.
+// State blob: a header naming the layout and the boundaries (the status words
+// record which neighbours were fluid or liquid, which depends on them), then
+// the current populations, status words, solute code words, solid volumes,
+// rho_max partials and balance records.
 struct StateHeader {
   char magic[8];
   uint32_t abi;
   int32_t nx, ny, pitch, precision, ns, seg_rows, nitems;
+  int32_t per_x, per_y;  // 0 wall, 1 periodic; per_y 2: free outlet at the top
   int64_t steps;
   uint64_t fbytes, gbytes, tbytes, cbytes, vbytes, rbytes, lbytes;
 };
-static const char STATE_MAGIC[8] = {'L', 'B', 'R', 'X', 'S', 'T', '0', '1'};
+static const char STATE_MAGIC[8] = {'L', 'B', 'R', 'X', 'S', 'T', '0', '2'};
 
 StateHeader state_header(const lbrx_ctx* x) {
   const KConst& c = x->c;
@@ -2622,6 +2625,8 @@ StateHeader state_header(const lbrx_ctx* x) {
   h.ns = c.ns;
   h.seg_rows = c.seg_rows;
   h.nitems = c.nitems;
+  h.per_x = c.per_x;
+  h.per_y = c.per_y;
   h.steps = x->steps;
   h.fbytes = c.fbytes;
   h.gbytes = c.gbytes;
@@ -2682,7 +2687,7 @@ lbrx_status lbrx_load_state(lbrx_ctx* x, const void* buf, uint64_t bytes) {
   mine.steps = h.steps;
   if (std::memcmp(&h, &mine, sizeof h) != 0)
     return set_err(x, LBRX_E_INVAL, "the state was saved from a context of another layout "
-                                    "(lattice size, precision, species count, seg_rows or ABI version)");
+                                    "(lattice size, boundaries, precision, species count, seg_rows or ABI version)");
   if (h.steps < 0 || bytes < state_size(h)) return set_err(x, LBRX_E_INVAL, "state buffer too small");
   HIPCHK(x, hipSetDevice(x->device));
   HIPCHK(x, hipStreamSynchronize(x->stream));
