@@ -34,19 +34,22 @@ def _lbrx():
     return Lbrx
 
 
-@pytest.mark.parametrize("case", ["droplet-ns2", "porous-ns4", "porous-ns8"])
+@pytest.mark.parametrize("case", ["droplet-ns2", "porous-ns4", "porous-ns8", "porous-ns1", "porous-ns3",
+                                  "porous-ns5", "porous-ns7"])
 @pytest.mark.parametrize("precision", ["f16dev", "bf16dev"])
 def test_initial_state_reads_back(precision, case):
     """Step 0 exported from 16-bit storage: densities and concentrations within
     the encoding bound (every node reads its own slots at step 0).  Two
     species use pair slots; four and eight, one and two slots of four species
-    (eight also a second word of solute reference codes)."""
+    (eight also a second word of solute reference codes); odd counts a padded
+    half pair (five and seven with the second code word)."""
     if case == "droplet-ns2":
         p = W.config0()
     else:
         p = W.config1(nx=130, ny=70, seed=11)
-        if case == "porous-ns8":
-            p = species_variant(p, 8)
+        ns = int(case.split("-ns")[1])
+        if ns != 4:
+            p = species_variant(p, ns)
     g = _lbrx()(p, precision)
     G = g.fields()
     fl = p.type0 == 0
