@@ -90,11 +90,13 @@ def test_outlet_request_in_the_mix():
             assert np.array_equal(a.fields[k], b.fields[k]), (a.rid, k)
 
 
-def test_served_fp64_request_matches_oracle():
-    """One FP64 request served in a mix of FP32 and FP16-storage requests that
-    arrive while others run (each precision batched with its own): when it
-    completes, its fields equal the oracle's after the same step count within
-    1e-12 (max-norm relative), node masks identical."""
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_served_request_matches_oracle(precision, tol):
+    """One FP64 (FP32) request served in a mix of FP32 and FP16-storage
+    requests that arrive while others run (each precision batched with its
+    own, the FP32 one with the other FP32 requests): when it completes, its
+    fields equal the oracle's after the same step count within 1e-12 (1e-5),
+    max-norm relative, node masks identical."""
     import os
     import sys
 
@@ -108,17 +110,17 @@ def test_served_fp64_request_matches_oracle():
     reqs = serve.poisson_requests(6, 0.003, seed=11, steps=(40, 100), sizes=(64, 128),
                                   precisions=("f32", "f16dev"))
     prob = W.batch_instance(4242, smin=80, smax=120)
-    reqs.insert(3, serve.Request(99, prob, 70, "f64", reqs[2].arrival))
+    reqs.insert(3, serve.Request(99, prob, 70, precision, reqs[2].arrival))
     stats = serve.Server(tick=20, keep_fields=True).run(reqs)
     print("served", stats, flush=True)
     (r,) = [q for q in reqs if q.rid == 99]
     assert r.status == "ok", r.status
     o = OracleSim(prob)
     o.step(70)
-    errs, masks, near = compare(r.fields, o.fields(), prob, 1e-12)
-    print(f"[served f64 {prob.name}] " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()) + f" masks={masks}",
-          flush=True)
+    errs, masks, near = compare(r.fields, o.fields(), prob, tol)
+    print(f"[served {precision} {prob.name}] " + " ".join(f"{k}={v:.2e}" for k, v in errs.items())
+          + f" masks={masks}", flush=True)
     assert masks
     for k, v in errs.items():
-        assert v <= 1e-12, (k, v)
+        assert v <= tol, (k, v)
     o.close()
