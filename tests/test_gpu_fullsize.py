@@ -5,9 +5,9 @@ The 1024 x 512 porous medium is compared field by field against the FP64
 oracle (run on the host's cores; its balances stay serial, so the result is
 the single-thread one) in FP64 and FP32 through 1000 steps, and the 16-bit
 storage forms are measured against it per field; the 4096 x 4096 roofline
-workload is compared field by field for a few FP32 steps and then checked,
-after many more GPU steps, on properties that hold at any size: the mass
-balance closes with the ledger and the masks stay consistent.
+workload is compared field by field for 2 and 20 FP32 steps (2 in FP64) and
+then checked, after many more GPU steps, on properties that hold at any size:
+the mass balance closes with the ledger and the masks stay consistent.
 """
 import os
 import sys
@@ -148,16 +148,17 @@ def test_porous_1024x512_16bit_storage(porous_oracle, precision):
 
 
 def test_porous_4096_full_field_and_balances():
-    """The 4096 x 4096 roofline workload in FP32: every field after 2 steps
-    against the oracle; then 200 more GPU steps close the mass ledger
+    """The 4096 x 4096 roofline workload in FP32: every field after 2 and 20
+    steps against the oracle; then 200 more GPU steps close the mass ledger
     (initial mass + sources + injections - removals = current mass, per
     component, to FP32 summation accuracy) and keep every liquid node fluid."""
     prob = W.config2()
     g = _lbrx()(prob, "f32")
     o = OracleSim(prob, threads=THREADS)
-    o.step(2)
-    g.step(2)
-    _check(g.fields(), o.fields(), prob, 1e-5, "porous-4096 f32 2")
+    for n in (2, 20):
+        o.step(n - o.steps_done)
+        g.step(n - g.steps_done)
+        _check(g.fields(), o.fields(), prob, 1e-5, f"porous-4096 f32 {n}")
     o.close()
     del o
     g.step(200)
@@ -176,4 +177,17 @@ def test_porous_4096_full_field_and_balances():
     rtol = 202 * 18 * 2.0 ** -24
     assert np.allclose(M, bal, rtol=rtol, atol=0)
     assert not np.any(F["liquid"].astype(bool) & ~fl)
+    g.close()
+
+
+def test_porous_4096_fp64_full_field():
+    """The 4096 x 4096 workload in FP64 storage and arithmetic: every field
+    of every node within 1e-12 of the oracle after 2 steps, masks identical."""
+    prob = W.config2()
+    g = _lbrx()(prob, "f64")
+    o = OracleSim(prob, threads=THREADS)
+    o.step(2)
+    g.step(2)
+    _check(g.fields(), o.fields(), prob, 1e-12, "porous-4096 f64 2")
+    o.close()
     g.close()
