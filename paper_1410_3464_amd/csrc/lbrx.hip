@@ -579,6 +579,8 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
   // exactly), so that rounding does not drift the balances step after step
   constexpr bool SFORM = std::is_same<T, float>::value && !DEV;
   constexpr bool REFS = DEV || SFORM;  // flow reference codes in the status words
+  // row R's homogeneous reaction sources formed while row R + 1 is pulled
+  constexpr bool EARLY_RX = !std::is_same<T, double>::value && SM != SM_OUT;
   // this simulation's top side is a free outlet (only in SM_OUT kernels; a
   // batch of mixed simulations runs them all in one)
   const bool outy = SM == SM_OUT && A.c.per_y == 2;
@@ -952,6 +954,37 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
   double l_vdv = 0.0;
   T my_rmax = T(0);
 
+  // Homogeneous reactions at a liquid node (Eq. 5a, 5c, 27, 28): the species
+  // sources Sk (net stoichiometric coefficients times the rates) and the gas
+  // component's source Sg (the liquid component's is -Sg), added to the
+  // node's balances.  nbt: the solid types among its D2Q5 neighbours, for
+  // surface-enhanced rates.
+  auto hom_sources = [&](const Mom<T, NS>& m, uint32_t nbt, T (&Sk)[NSA], T& Sg) {
+    const T r2 = m.rho[1];
+    for (int r = 0; r < c.nhom; ++r) {
+      T Rr;
+      // (behind the uniform test, the rate stays a scalar operand)
+      T kr = k.hk[r];
+      if (c.any_hsurf && (c.hsurf[r] & nbt)) kr = k.hks[r];
+      if (c.hkind[r] == HOM_FIRST) {
+        Rr = kr * sel<NS>(m.C, c.hre0[r]);
+      } else if (c.hkind[r] == HOM_BI) {
+        Rr = kr * sel<NS>(m.C, c.hre0[r]) * sel<NS>(m.C, c.hre1[r]);
+      } else {
+        T cg = cdiv<T>(r2, k.hMgas[r], k.r_hMgas[r]);
+        if (cg < T(0)) cg = T(0);
+        Rr = kr * (sel<NS>(m.C, c.hre0[r]) -
+                   cdiv<T>(sel<NS>(m.C, c.hpr0[r]) * dsqrt<T>(cg), k.hKeq[r], k.r_hKeq[r]));
+        Sg += T(0.5) * Rr * k.hMgas[r];
+      }
+#pragma unroll
+      for (int kk = 0; kk < NS; ++kk) Sk[kk] += k.hnu[r][kk] * Rr;
+    }
+    l_msrc += (double)Sg;
+#pragma unroll
+    for (int kk = 0; kk < NS; ++kk) l_ssrc[kk] += (double)Sk[kk];
+  };
+
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 
   // The march: iteration R pulls row R + 1 into the ring and collides row R.
@@ -976,6 +1009,12 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
     const double v_nn = EXPORT ? 0.0 : bload<double>(rv, gate(vpre, ((unsigned)Rn * upitch + (unsigned)X) * 8u), 0u);
     T fn[2][9], gn[NSA][5];
     Mom<T, NS> mn;
+    // row R's node-local results formed while the pull of row R + 1 is in
+    // flight (see below)
+    T e_Sk[NSA], e_Sg = T(0);
+#pragma unroll
+    for (int kk = 0; kk < NSA; ++kk) e_Sk[kk] = T(0);
+    uint32_t e_cwc0 = 0u, e_cwc1 = 0u;
     {
       // ---------------------------------------------------- phase 1, row R + 1
       int Yw = Rn;
@@ -987,6 +1026,55 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
       const bool validf = indom && (t == T_FLUID || (w & TB_STR));
       const bool withg = indom && sf_of(w) != SF_NONE;
       pull(co, rowin ? Yw : 0, w, validf, withg, fn, gn);
+      // While those loads are in flight: row R's work that needs nothing of
+      // row R + 1 (its own status word, its liquid mark staged in the ring
+      // last iteration, its moments).  16-bit storage: the node's solute
+      // reference codes for its own pull next step, from its staged moments
+      // (the references its neighbours code the populations they send it
+      // against).  Solute amendments (Sec. 4.5; Step 2): a node that turns
+      // liquid without content starts at zero (a node that was sending shares
+      // has handed its content over), and a subtracted species is derived
+      // (Sec. 4.1).  Then the homogeneous reaction sources, unless a rate
+      // depends on the solid types around the node (row R + 1 among them);
+      // the FP64 and free-outlet kernels form the sources in phase 2 (in the
+      // FP64 outlet kernel with two species, forming them here gave wrong
+      // product concentrations that came and went with unrelated code
+      // changes; its cause was not found).
+      if (R >= y0) {
+        Mom<T, NS>& m = mc;
+        T(&g)[NSA][5] = gc;
+        const uint32_t w0 = w_cur;
+        const bool fluid0 = colin && (int)(w0 & TB_T) == T_FLUID;
+        const int sf0 = colin ? sf_of(w0) : SF_NONE;
+        const bool liq0 = colin && is_liq(flags_of<T>(L.pq[s0][lane + 1].fl));
+        if constexpr (DEV) {
+#pragma unroll
+          for (int kk = 0; kk < NS; ++kk) {
+            const uint32_t cc = ref_code(m.C[kk], k.rbc[kk], SHC, MAXC) << (8 * (kk & 3));
+            if (kk < 4) e_cwc0 |= cc;
+            else e_cwc1 |= cc;
+          }
+        }
+        if (NS > 0) {
+          if (liq0 && (sf0 == SF_NONE || sf0 == SF_SHARE)) {
+#pragma unroll
+            for (int kk = 0; kk < NSA; ++kk) {
+              m.C[kk] = T(0);
+#pragma unroll
+              for (int a = 0; a < 5; ++a) g[kk][a] = T(0);
+            }
+          }
+          if (NS > 1 && c.sub >= 0) {
+            T cd[NSA];
+#pragma unroll
+            for (int kk = 0; kk < NSA; ++kk) cd[kk] = m.C[kk];
+            subtract(cd, m.rho[0]);
+#pragma unroll
+            for (int kk = 0; kk < NSA; ++kk) m.C[kk] = liq0 ? cd[kk] : m.C[kk];
+          }
+        }
+        if (EARLY_RX && !EXPORT && !c.any_hsurf && colown && fluid0 && liq0) hom_sources(m, 0u, e_Sk, e_Sg);
+      }
       moments(fn, gn, w, validf, mn);
       unsigned errf = 0;
       const bool bad = validf && (!(mn.rho[0] >= T(0)) || !(mn.rho[1] >= T(0)) || (fluid && !(mn.rho[0] + mn.rho[1] > T(0))));
@@ -1063,20 +1151,9 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
 
       // Solute amendments (Sec. 4.5; Step 2): the shares in transit from D2Q5
       // neighbours that left the liquid set last step reach this node if it
-      // was liquid then; a node that turns liquid without content starts at
-      // zero (a node that was sending shares has handed its content over).
-      // 16-bit storage: the node's solute reference codes for its own pull
-      // next step, from the moments staged in the ring (the references its
-      // neighbours code the populations they send it against)
-      uint32_t cwc0 = 0u, cwc1 = 0u;
-      if constexpr (DEV) {
-#pragma unroll
-        for (int kk = 0; kk < NS; ++kk) {
-          const uint32_t cc = ref_code(m.C[kk], k.rbc[kk], SHC, MAXC) << (8 * (kk & 3));
-          if (kk < 4) cwc0 |= cc;
-          else cwc1 |= cc;
-        }
-      }
+      // was liquid then (the node's own amendments were made while the pull
+      // was in flight).
+      const uint32_t cwc0 = e_cwc0, cwc1 = e_cwc1;
       T Cin[NSA];
 #pragma unroll
       for (int kk = 0; kk < NSA; ++kk) Cin[kk] = T(0);
@@ -1095,22 +1172,6 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
 #pragma unroll
               for (int kk = 0; kk < NS; ++kk) Cin[kk] += L.C[kk][sl][lx];
             }
-        }
-        if (liq && (sf == SF_NONE || sf == SF_SHARE)) {
-#pragma unroll
-          for (int kk = 0; kk < NSA; ++kk) {
-            m.C[kk] = T(0);
-#pragma unroll
-            for (int a = 0; a < 5; ++a) g[kk][a] = T(0);
-          }
-        }
-        if (NS > 1 && c.sub >= 0) {
-          T cd[NSA];
-#pragma unroll
-          for (int kk = 0; kk < NSA; ++kk) cd[kk] = m.C[kk];
-          subtract(cd, m.rho[0]);
-#pragma unroll
-          for (int kk = 0; kk < NSA; ++kk) m.C[kk] = liq ? cd[kk] : m.C[kk];
         }
       }
 
@@ -1214,42 +1275,21 @@ __global__ __launch_bounds__(64 * WPB, min_waves<T>()) void k_step(const LaunchA
           LA.out[2 * c.plane + idx] = (double)urx;
           LA.out[3 * c.plane + idx] = (double)ury;
         } else {
-          // homogeneous reactions at liquid nodes (Eq. 5a, 5c, 27, 28); the
-          // species sources are the net stoichiometric coefficients times the rates
+          // homogeneous reaction sources: formed while the pull was in
+          // flight, or here where a rate depends on the neighbours' solid
+          // types (surface-enhanced rates) and in the FP64 and outlet kernels
           T Sk[NSA];
 #pragma unroll
-          for (int kk = 0; kk < NSA; ++kk) Sk[kk] = T(0);
-          T Sg = T(0);  // gas component's source; the liquid component's is -Sg
-          if (liq) {
-            // solid types among the D2Q5 neighbours (surface-enhanced rates)
+          for (int kk = 0; kk < NSA; ++kk) Sk[kk] = e_Sk[kk];
+          T Sg = e_Sg;
+          if (liq && (!EARLY_RX || c.any_hsurf)) {
             uint32_t nbt = 0u;
             if (c.any_hsurf) {
 #pragma unroll
               for (int a = 1; a < 5; ++a)
                 if (!(nt[a] & TB_WALL)) nbt |= 1u << (nt[a] & TB_T);
             }
-            for (int r = 0; r < c.nhom; ++r) {
-              T Rr;
-              // (behind the uniform test, the rate stays a scalar operand)
-              T kr = k.hk[r];
-              if (c.any_hsurf && (c.hsurf[r] & nbt)) kr = k.hks[r];
-              if (c.hkind[r] == HOM_FIRST) {
-                Rr = kr * sel<NS>(m.C, c.hre0[r]);
-              } else if (c.hkind[r] == HOM_BI) {
-                Rr = kr * sel<NS>(m.C, c.hre0[r]) * sel<NS>(m.C, c.hre1[r]);
-              } else {
-                T cg = cdiv<T>(r2, k.hMgas[r], k.r_hMgas[r]);
-                if (cg < T(0)) cg = T(0);
-                Rr = kr * (sel<NS>(m.C, c.hre0[r]) -
-                           cdiv<T>(sel<NS>(m.C, c.hpr0[r]) * dsqrt<T>(cg), k.hKeq[r], k.r_hKeq[r]));
-                Sg += T(0.5) * Rr * k.hMgas[r];
-              }
-#pragma unroll
-              for (int kk = 0; kk < NS; ++kk) Sk[kk] += k.hnu[r][kk] * Rr;
-            }
-            l_msrc += (double)Sg;
-#pragma unroll
-            for (int kk = 0; kk < NS; ++kk) l_ssrc[kk] += (double)Sk[kk];
+            hom_sources(m, nbt, Sk, Sg);
           }
           const T Ss[2] = {T(0) - Sg, Sg};
           // flow collision (Eq. 6, 8)
