@@ -141,8 +141,9 @@ typedef struct {
   const double* C0;         /* used at nodes that start liquid; may be NULL if n_species == 0 */
   /* work decomposition: rows per work item of the step kernel (each item is
      62 columns by seg_rows rows, one 64-lane wavefront that also pulls the
-     column on either side), 1..30; 0 picks 16.  It changes the speed, not
-     the result. */
+     column on either side), 1..30; 0 picks 16, or 8, 4 or 2 for a lattice
+     whose items would not fill the device.  It changes the speed and not
+     the fields (the balance sums, added per item, to rounding). */
   int32_t seg_rows;
   /* effective mass psi_1 = sqrt(psi_prefactor (p_EOS - rho1/3) / G11) (Eq. 13).
      0 selects 2, the value for which the weights of Eq. 11 reproduce the EOS

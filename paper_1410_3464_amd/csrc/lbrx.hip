@@ -1867,6 +1867,19 @@ __global__ __launch_bounds__(LSUM_THREADS) void k_ledger_sum(const double* led, 
 // ---------------------------------------------------------------- host side
 constexpr int SEG_ROWS = 16;      // default rows per item (LBRX_SEG_ROWS overrides, 1..HMAX)
 constexpr int SEG_ROWS_F64 = 16;  // FP64 storage (one wavefront per SIMD): taller items
+// Rows per item when the caller names none: SEG_ROWS, halved (down to 2) while
+// the lattice has fewer items than the device holds wavefronts at once (2 per
+// SIMD on 256 CUs, 1 with FP64 storage).  A lattice that does not fill the
+// device takes as long per step as one item's march down its rows, so shorter
+// items finish sooner even though each pulls two ring rows more per H rows.
+int default_seg_rows(int nx, int ny, int precision) {
+  const bool f64 = precision == LBRX_F64;
+  const long long slots = f64 ? 1024 : 2048;
+  const long long strips = (nx + IW - 1) / IW;
+  int h = f64 ? SEG_ROWS_F64 : SEG_ROWS;
+  while (h > 2 && strips * ((ny + h - 1) / h) < slots) h /= 2;
+  return h;
+}
 // Steps per captured HIP graph of launches: a multiple of 6, the period of
 // the step phases (buffer parity and rho_max slot), so that one graph serves
 // every replay that starts at a step count divisible by 6.
@@ -2391,7 +2404,7 @@ lbrx_status lbrx_create(const lbrx_params* p, void* hip_stream, lbrx_ctx** out) 
   x->precision = p->precision;
   x->esz = storage_bytes(p->precision);
   c.sg = species_group(c.ns, (int)x->esz);
-  c.seg_rows = p->seg_rows > 0 ? p->seg_rows : (p->precision == LBRX_F64 ? SEG_ROWS_F64 : SEG_ROWS);
+  c.seg_rows = p->seg_rows > 0 ? p->seg_rows : default_seg_rows(p->nx, p->ny, p->precision);
   if (const char* e = getenv("LBRX_SEG_ROWS")) {
     const int v = atoi(e);
     if (v >= 1 && v <= HMAX) c.seg_rows = v;

@@ -98,7 +98,7 @@ def footprint_bytes(prob, precision):
     esz = ESZ[precision]
     pops = 18 * plane * esz + 10 * ((ns + 1) // 2) * plane * esz
     words = plane * 4 * (1 + (((ns + 3) // 4) if esz == 2 else 0))
-    items = -(-nx // 62) * ((ny + 7) // 8)  # balance records: items of 62 columns, 8 rows or more
+    items = -(-nx // 62) * ((ny + 1) // 2)  # balance records: items of 62 columns, 2 rows or more
     return 2 * (pops + words) + plane * 8 + items * 38 * 8 + (4 + ns) * plane * 8
 
 

@@ -90,13 +90,14 @@ def test_poisson_requests_and_summary():
 def test_footprint_counts_every_buffer():
     """FP32, 4 species, 64 x 64: two buffers of 18 flow and 20 solute values
     and a status word per node, solid volumes, balance records of items of 62
-    columns by 8 rows (or more) and the read-out planes; 16-bit storage halves
-    the populations and adds the code words."""
+    columns by 2 rows (or more: the shortest item a lattice is given) and the
+    read-out planes; 16-bit storage halves the populations and adds the code
+    words."""
     from paper_1410_3464_amd import serve
 
     p = W.config1(nx=64, ny=64, seed=1)
     plane = 64 * 64
-    items = 2 * 8
+    items = 2 * 32
     want = 2 * (38 * plane * 4 + plane * 4) + plane * 8 + items * 38 * 8 + 8 * plane * 8
     assert serve.footprint_bytes(p, "f32") == want
     want16 = 2 * (38 * plane * 2 + plane * 4 * 2) + plane * 8 + items * 38 * 8 + 8 * plane * 8
