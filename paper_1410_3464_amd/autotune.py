@@ -1,8 +1,9 @@
 """Tile-schedule autotuner for the step kernel.
 
 The kernel's work item is 62 columns by `seg_rows` rows, one wavefront.  Short
-items balance better on small lattices; long items repeat fewer ring rows (two
-per item) on large ones.  The best value depends on lattice size, storage
+items balance better on small lattices, and on a lattice that does not fill the
+device they cut the time of an item's march, which is then the time of a step;
+long items repeat fewer ring rows (two per item) on large ones.  The best value depends on lattice size, storage
 precision and on how full the device is, so it is measured: each candidate runs
 a few steps on the GPU and the fastest is kept per (size class, precision,
 species count, context).  Alone, a lattice is timed by itself; for batched runs
@@ -14,7 +15,7 @@ from __future__ import annotations
 
 import math
 
-CANDIDATES = (8, 12, 16, 24, 30)
+CANDIDATES = (2, 4, 8, 12, 16, 24, 30)
 _cache: dict = {}
 
 
